@@ -1,0 +1,300 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself through the same formula: each
+check uses a different route (dense Pauli matrices, closed forms printed in the
+paper, group invariants, Parseval, known-answer vectors, statistics).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+PAULI = {
+    (0, 0): np.eye(2, dtype=complex),
+    (1, 0): np.array([[0, 1], [1, 0]], dtype=complex),
+    (0, 1): np.array([[1, 0], [0, -1]], dtype=complex),
+    (1, 1): np.array([[0, -1j], [1j, 0]], dtype=complex),
+}
+
+
+def dense_pauli(n, x, z):
+    """Hermitian Pauli with X on the set bits of x and Z on those of z (Y where both),
+    qubit j = bit j, as an explicit 2^n x 2^n matrix built from Kronecker products."""
+    m = np.array([[1.0 + 0j]])
+    for j in range(n):                       # qubit j becomes the new most significant factor
+        m = np.kron(PAULI[((x >> j) & 1, (z >> j) & 1)], m)
+    return m
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (3, 3), (4, 4)])
+def test_bruteforce_matches_dense_pauli_matrices(n, seed):
+    psi = synth.haar_state(n, seed)
+    c = oracle.bruteforce(psi)
+    d = 1 << n
+    for x in range(d):
+        for z in range(d):
+            ref = np.vdot(psi, dense_pauli(n, x, z) @ psi)
+            assert abs(c[x, z] - ref) < 1e-13
+
+
+def test_bruteforce_single_qubit_bloch_values_of_T():
+    # |T> = (|0> + e^{i pi/4}|1>)/sqrt2 has Bloch vector (cos pi/4, sin pi/4, 0)
+    c = oracle.bruteforce(synth.T_STATE)
+    s = 1 / math.sqrt(2)
+    assert abs(c[0, 0] - 1) < 1e-15          # I
+    assert abs(c[1, 0] - s) < 1e-15          # X
+    assert abs(c[1, 1] - s) < 1e-15          # Y
+    assert abs(c[0, 1]) < 1e-15              # Z
+
+
+def test_purity_sum_rule():
+    # sum_P c_P^2 / d = Tr rho^2 = 1 for a pure state
+    for n, seed in [(3, 7), (5, 8), (7, 9)]:
+        c = oracle.bruteforce(synth.haar_state(n, seed))
+        assert abs(np.sum(np.abs(c) ** 2) / 2 ** n - 1) < 1e-12
+        assert np.max(np.abs(c.imag)) < 1e-14          # Hermitian Paulis have real expectations
+
+
+# --------------------------------------------------------------------------- Algorithm 1
+
+@pytest.mark.parametrize("n,seed", [(2, 11), (5, 12), (7, 13)])
+def test_alg1_equals_bruteforce_definition(n, seed):
+    psi = synth.haar_state(n, seed)
+    c = oracle.bruteforce(psi)
+    d = 1 << n
+    a2 = np.abs(c) ** 2
+    # per family: the FWHT spectrum carries every |c| of the family, with phase (-i)^{|x&z|}
+    for x in range(d):
+        F = oracle.spectrum(psi, x)
+        ph = np.array([(-1j) ** bin(x & z).count("1") for z in range(d)])
+        assert np.max(np.abs(ph * F - c[x])) < 1e-13
+    r = oracle.eval_x(psi, np.arange(d), eps=1e-7, max_alpha=4)
+    for al in (2, 3, 4):
+        ref = np.sum(a2 ** al, axis=1) / d ** al
+        assert np.allclose(r["m"][:, al - 2], ref, rtol=1e-12, atol=0)
+    ent = np.sum(np.where(a2 > 0, a2 * np.log2(np.where(a2 > 0, a2, 1)), 0), axis=1)
+    assert np.allclose(r["ent"], ent, rtol=1e-11, atol=1e-15)
+    assert np.allclose(r["p"], np.sum(a2, axis=1) / d, rtol=1e-12)
+    full = oracle.alg1(psi)
+    for al in (2, 3, 4):
+        M = math.log2(np.sum(a2 ** al) / d ** al) / (1 - al) - n
+        assert abs(full["M"][al] - M) < 1e-11
+    assert abs(full["M1"] - (-np.sum(np.where(a2 > 0, a2 * np.log2(np.where(a2 > 0, a2, 1)), 0)) / d)) < 1e-11
+
+
+def test_marginal_is_parseval_of_the_family_spectrum():
+    # p(x) computed directly from q = |psi|^2 equals sum_z |F_x(z)|^2 / d; sum_x p(x) = 1
+    n = 8
+    psi = synth.haar_state(n, 21)
+    xs = np.arange(1 << n, dtype=np.uint64)
+    p_direct = oracle.marginal(psi, xs)
+    p_fwht = oracle.eval_x(psi, xs)["p"]
+    assert np.allclose(p_direct, p_fwht, rtol=1e-12, atol=1e-18)
+    assert abs(p_direct.sum() - 1) < 1e-13
+
+
+def test_psi_m_closed_forms():
+    g = gold("paper_values.json")
+    for n in (4, 6, 8, 10):
+        psi = synth.psi_m_state(n)             # |T> on qubits 0..n/2-1 (sector A), |0> on the rest (B)
+        d = 1 << n
+        r = oracle.eval_x(psi, np.arange(d))
+        m2 = r["m"][:, 0]
+        h = n // 2
+        for x in range(d):
+            xa, xb = x & ((1 << h) - 1), x >> h
+            ref = 0.0 if xb else 2.0 ** (-1.5 * n - bin(xa).count("1"))
+            assert abs(m2[x] - ref) <= 1e-14 * max(ref, 2.0 ** (-1.5 * n))
+        assert abs(m2.mean() / g["psi_m_mean"]["base"] ** (n / 2) - 1) < 1e-12
+        # exact fluctuation ratio: population std over x != 0 divided by the mean over all x
+        r2 = np.std(m2[1:]) / m2.mean()
+        ref = (8 / 3) ** (n / 2) * math.sqrt(((5 / 4) ** (n / 2) - 1) / (4 ** (n / 2) - 1)
+                                            - ((1.5 ** (n / 2) - 1) ** 2) / (4 ** (n / 2) - 1) ** 2)
+        assert abs(r2 / ref - 1) < 1e-10
+        full = oracle.alg1(psi)
+        assert abs(full["M"][2] - h * math.log2(4 / 3)) < 1e-12
+
+
+def test_psi_m_local_factors():
+    g = gold("paper_values.json")["psi_m_local_factors"]
+    cT = np.abs(oracle.bruteforce(synth.T_STATE)) ** 4
+    c0 = np.abs(oracle.bruteforce(np.array([1, 0], dtype=complex))) ** 4
+    assert abs(cT[0, 0] + cT[0, 1] - g["T_IZ"]) < 1e-14
+    assert abs(cT[1, 0] + cT[1, 1] - g["T_XY"]) < 1e-14
+    assert abs(c0[0, 0] + c0[0, 1] - g["zero_IZ"]) < 1e-14
+    assert abs(c0[1, 0] + c0[1, 1] - g["zero_XY"]) < 1e-14
+
+
+def _random_clifford_state(n, layers, seed, t_on=()):
+    gates = synth.random_brickwall_clifford(n, layers, seed)
+    k, q, m = synth.gates_to_arrays(gates)
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0] = 1
+    return oracle.apply_gates(psi, k, q, m)
+
+
+@pytest.mark.parametrize("n,seed", [(4, 31), (6, 32), (8, 33)])
+def test_stabilizer_states_have_zero_magic(n, seed):
+    psi = _random_clifford_state(n, 3 * n, seed)
+    r = oracle.alg1(psi)
+    for al in (2, 3, 4):
+        assert abs(r["M"][al]) < 1e-10
+    assert abs(r["M1"]) < 1e-10
+    assert r["nu_cnt"] == 2 ** n and r["nu"] == 0.0
+
+
+@pytest.mark.parametrize("n,seed", [(5, 41), (6, 42), (8, 43)])
+def test_T_on_stabilizer_product_additivity(n, seed):
+    # single-shot protocol at N_C = 0: M_2 = log2(4/3) per qubit whose state is an X or Y eigenstate
+    labels = synth.stabilizer_product_spec(n, seed)
+    psi = synth.states.stabilizer_product(labels, t_on=set(range(n)))
+    n_xy = sum(lab[0] != "z" for lab in labels)
+    r = oracle.alg1(psi)
+    assert abs(r["M"][2] - n_xy * math.log2(4 / 3)) < 1e-11
+    assert abs(r["M1"] - 0.5 * n_xy) < 1e-11      # Shannon limit: 1/2 per such qubit
+    assert abs(r["nu"] - n_xy) < 1e-12
+    assert (r["nu_cnt"] & (r["nu_cnt"] - 1)) == 0  # a group order: power of two
+
+
+def test_clifford_invariance_of_magic_and_nullity():
+    n = 6
+    labels = synth.stabilizer_product_spec(n, 51)
+    psi = synth.states.stabilizer_product(labels, t_on=set(range(n)))
+    before = oracle.alg1(psi)
+    k, q, m = synth.gates_to_arrays(synth.random_brickwall_clifford(n, 2 * n, 52))
+    after = oracle.alg1(oracle.apply_gates(psi, k, q, m))
+    for al in (2, 3, 4):
+        assert abs(before["M"][al] - after["M"][al]) < 1e-10
+    assert abs(before["M1"] - after["M1"]) < 1e-10
+    assert before["nu_cnt"] == after["nu_cnt"]
+
+
+def test_apply_gates_matches_dense_embedding():
+    n = 4
+    psi = synth.haar_state(n, 61)
+    gates = synth.random_brickwall_clifford(n, 3, 62) + [synth.t_gate(2)]
+    k, q, m = synth.gates_to_arrays(gates)
+    ref = psi.copy()
+    for gt in gates:
+        U = np.zeros((1 << n, 1 << n), dtype=complex)
+        for b in range(1 << n):
+            if gt.kind == synth.GATE_2Q:
+                j = ((b >> gt.q0) & 1) + 2 * ((b >> gt.q1) & 1)
+                base = b & ~((1 << gt.q0) | (1 << gt.q1))
+                for jo in range(4):
+                    bo = base | ((jo & 1) << gt.q0) | ((jo >> 1) << gt.q1)
+                    U[bo, b] += gt.mat[jo, j]
+            else:
+                U[b, b] = gt.mat[(b >> gt.q0) & 1]
+        ref = U @ ref
+    out = oracle.apply_gates(psi, k, q, m)
+    assert np.max(np.abs(out - ref)) < 1e-13
+
+
+def test_haar_average_close_to_formula():
+    g = gold("paper_values.json")
+    assert g["haar_m2"]["formula"] == "log2(2^N+3)-2"
+    for n, seed in [(8, 71), (10, 72)]:
+        r = oracle.alg1(synth.haar_state(n, seed))
+        assert abs(r["M"][2] - (math.log2(2 ** n + 3) - 2)) < 0.05
+
+
+def test_nullity_tolerance_is_the_papers():
+    assert gold("paper_values.json")["nullity_eps"]["eps"] == 1e-7
+
+
+# --------------------------------------------------------------------------- random draws
+
+def test_philox_known_answer_vectors():
+    for v in gold("philox_kat.json")["vectors"]:
+        out = oracle.philox4x32_10([int(c, 16) for c in v["ctr"]], [int(k, 16) for k in v["key"]])
+        assert out == [int(o, 16) for o in v["out"]]
+
+
+def test_uniform_sampler_range_and_chi2():
+    n = 5
+    xs = oracle.sample_uniform_nz(n, 123, 0, 62000)
+    assert xs.min() >= 1 and xs.max() <= 31
+    cnt = np.bincount(xs.astype(np.int64), minlength=32)[1:]
+    e = len(xs) / 31
+    chi2 = np.sum((cnt - e) ** 2 / e)
+    assert chi2 < 30 + 6 * math.sqrt(60)      # 30 degrees of freedom
+
+
+def test_marginal_sampler_chi2_against_exact_table():
+    n = 6
+    psi = synth.haar_state(n, 81)
+    xs, failed = oracle.sample_marginal_nz(psi, 99, 0, 100000)
+    assert failed == 0 and xs.min() >= 1
+    p = oracle.marginal(psi, np.arange(1 << n, dtype=np.uint64))
+    e = len(xs) * p[1:] / (1 - p[0])
+    cnt = np.bincount(xs.astype(np.int64), minlength=1 << n)[1:]
+    chi2 = np.sum((cnt - e) ** 2 / e)
+    dof = (1 << n) - 2
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
+# --------------------------------------------------------------------------- estimators
+
+def test_uniform_estimator_is_unbiased():
+    n = 7
+    psi = synth.haar_state(n, 91)
+    d = 1 << n
+    r = oracle.eval_x(psi, np.arange(d))
+    m2 = r["m"][:, 0]
+    S = m2.sum()
+    ests = []
+    for s in range(400):
+        xs = oracle.sample_uniform_nz(n, 1000 + s, 0, 31)
+        ests.append(oracle.mc_uniform(n, m2[0], m2[xs.astype(np.int64)], 2)[0])
+    ests = np.array(ests)
+    assert abs(ests.mean() - S) < 5 * ests.std() / math.sqrt(len(ests))
+
+
+def test_marginal_estimator_is_unbiased_and_exact_for_alpha1():
+    n = 7
+    psi = _random_clifford_state(n, 4, 95)
+    psi = oracle.apply_gates(psi, *synth.gates_to_arrays([synth.t_gate(j) for j in range(n)]))
+    d = 1 << n
+    r = oracle.eval_x(psi, np.arange(d))
+    m2, p = r["m"][:, 0], r["p"]
+    S = m2.sum()
+    ests = []
+    for s in range(300):
+        xs, failed = oracle.sample_marginal_nz(psi, 2000 + s, 0, 31)
+        assert failed == 0
+        xi = xs.astype(np.int64)
+        ests.append(oracle.mc_marginal(m2[0], p[0], m2[xi], p[xi], 2)[0])
+        # with alpha = 1 the weight m_{1;x}/p(x) is 1: the estimate is exactly sum_x p(x) = 1
+        S1, se1, _ = oracle.mc_marginal(p[0], p[0], p[xi], p[xi], 1)
+        assert abs(S1 - 1) < 1e-12 and se1 < 1e-12
+    ests = np.array(ests)
+    assert abs(ests.mean() - S) < 5 * ests.std() / math.sqrt(len(ests))
+
+
+@pytest.mark.slow
+def test_haar_n24_ten_samples_worked_example():
+    # the paper's worked example: N = 24, N_MC = 10 -> M_2 = 21.9999(2), exact log2(2^24+3)-2
+    g = gold("paper_values.json")["haar_n24_nmc10"]
+    n, nmc = g["N"], g["n_mc"]
+    psi = synth.haar_state(n, synth.SEED_BASE + 24)
+    xs = np.concatenate([[0], oracle.sample_uniform_nz(n, 7, 0, nmc - 1)]).astype(np.uint64)
+    r = oracle.eval_x(psi, xs, max_alpha=2)
+    S, se, sM = oracle.mc_uniform(n, r["m"][0, 0], r["m"][1:, 0], 2)
+    M = oracle.M_from_S(n, S, 2)
+    exact = math.log2(2 ** n + 3) - 2
+    assert abs(M - exact) < 5 * max(sM, g["uncertainty"])
+    assert abs(M - g["value"]) < 0.002
