@@ -1,0 +1,186 @@
+/*
+ * pauliwht.h -- C ABI of the MI355X (gfx950) library for FWHT Pauli-string
+ * evaluation: stabilizer Renyi entropies and stabilizer nullity of an N-qubit
+ * state vector (Xiao & Ryu, "Exponentially Accelerated Sampling of Pauli Strings
+ * for Nonstabilizerness").
+ *
+ * What the library computes.  For every X-bitstring x, the family
+ * { <psi|P_{x,z}|psi> : z } is the Walsh-Hadamard transform over b of
+ *     f_x(b) = conj(psi(b)) psi(b ^ x)                       (Pauli labelling section)
+ * and one fast transform gives all 2^N values at O(N) cost per string.  Fused
+ * reductions over z give, per family,
+ *     p(x)   = m_{1;x} = sum_z |F|^2 / d                     (exact x-marginal)
+ *     ent(x) = sum_z |F|^2 log2 |F|^2                         (Shannon term, alpha = 1)
+ *     m[a]   = m_{a+2;x} = sum_z |F|^{2(a+2)} / d^{a+2}      (partial moments, alpha = 2, 3, 4)
+ *     nu(x)  = #{ z : ||F| - 1| < eps }                       (nullity count)
+ * and the estimators combine them (Algorithm 1 for the exact sweep; the Monte
+ * Carlo section and its error formula, Eq. stdM, for sampling).
+ *
+ * Conventions.
+ *   - Qubit j is bit j of the basis index (little endian); x and z are bit masks.
+ *   - The Hermitian Pauli of label (x, z) is i^{|x&z|} X^x Z^z (Y = iXZ), so
+ *     <psi|P|psi> = (-i)^{|x&z|} F_x(z), which is real.
+ *   - States are contiguous, interleaved (re, im): PW_C128 = 2 doubles per
+ *     amplitude (the transform runs in FP64), PW_C64 = 2 floats (FP32 transform).
+ *     Per-family sums are accumulated in FP64 in a fixed order, so results are
+ *     bitwise reproducible run to run.
+ *   - M_alpha = log2(S_alpha)/(1 - alpha) - N (Eq. SRE-def), M_1 = -(1/d) sum_x ent(x)
+ *     (the alpha -> 1 limit), nu = N - log2(nu_cnt).
+ *
+ * Ownership.  Device buffers (the state, the workspace) belong to the caller and
+ * are borrowed; the library never frees them.  Host arrays passed in or out are
+ * caller-allocated.  The library allocates device memory of its own only when no
+ * workspace was set (then it owns and frees it at pw_ctx_destroy).
+ *
+ * Streams.  All device work of a context is enqueued on the stream given at
+ * creation (NULL = the default stream).  Calls that return host results
+ * synchronise that stream before returning.
+ *
+ * Errors.  Every call returns a pw_status.  Out-parameters are written only on
+ * PW_OK.  pw_last_error() gives a message for the last failing call of the
+ * calling thread.  A context must not be used from two threads at once.
+ */
+#ifndef PAULIWHT_H
+#define PAULIWHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PW_API __attribute__((visibility("default")))
+#else
+#define PW_API
+#endif
+
+typedef struct pw_ctx_s* pw_ctx;
+
+typedef enum {
+    PW_OK = 0,
+    PW_ERR_ARG = 1,             /* null pointer, bad enum, bad count              */
+    PW_ERR_RANGE = 2,           /* qubit count or x outside the supported range   */
+    PW_ERR_NOT_NORMALIZED = 3,  /* |<psi|psi> - 1| above tolerance, or NaN/Inf     */
+    PW_ERR_NO_STATE = 4,        /* no state bound to the context                   */
+    PW_ERR_WORKSPACE = 5,       /* workspace too small                             */
+    PW_ERR_HIP = 6,             /* a HIP runtime call failed                       */
+    PW_ERR_TOLERANCE = 7,       /* nullity count is not a power of two            */
+    PW_ERR_UNSUPPORTED = 8      /* valid request this build does not handle        */
+} pw_status;
+
+typedef enum { PW_C128 = 0, PW_C64 = 1 } pw_dtype;
+
+typedef enum {
+    PW_SAMPLER_UNIFORM_NZ = 0,  /* x uniform over F_2^N \ {0} (Monte Carlo section)  */
+    PW_SAMPLER_MARGINAL_NZ = 1  /* x ~ p(x | x != 0), p the exact x-marginal          */
+} pw_sampler;
+
+/* Per-family results (one per x). */
+typedef struct {
+    uint64_t x;
+    double p;          /* m_{1;x}: exact x-marginal                                  */
+    double ent;        /* sum_z |F|^2 log2 |F|^2                                      */
+    double m[3];       /* m_{alpha;x}, alpha = 2, 3, 4                                */
+    double gap;        /* max |F| below 1 - eps (-1 if none): margin of the nullity test */
+    uint64_t nu;       /* #{z : ||F| - 1| < eps}                                      */
+} pw_xres;
+
+/* Whole-state results of pw_exact / pw_mc. */
+typedef struct {
+    double S[3];       /* sum_x m_{alpha;x}, alpha = 2, 3, 4 (estimate for pw_mc)     */
+    double S_se[3];    /* standard error of S (0 for pw_exact)                        */
+    double M[3];       /* M_alpha                                                      */
+    double M_se[3];    /* sigma_S / (|1-alpha| ln2 S)  (Eq. stdM)                      */
+    double L, L_se;    /* sum_x ent(x) and its standard error                          */
+    double M1, M1_se;  /* M_1 = -L/d                                                   */
+    double P;          /* sum_x p(x) over the families evaluated (1 for pw_exact)     */
+    double nullity;    /* N - log2 nu_cnt (pw_exact only; NaN for pw_mc)               */
+    uint64_t nu_cnt;   /* sum_x nu(x) (pw_exact only)                                  */
+    uint64_t n_samples;/* families evaluated, x = 0 included                           */
+    double r[3];       /* sample sd of the per-family terms / their mean (pw_mc)       */
+    double gap;        /* max over families of gap                                     */
+} pw_result;
+
+/* Message for the last failing call on this thread ("" if none).  Valid until
+ * the next pw_* call on this thread. */
+PW_API const char* pw_last_error(void);
+
+/* Library version string. */
+PW_API const char* pw_version(void);
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t, borrowed; NULL = default stream). */
+PW_API pw_status pw_ctx_create(pw_ctx* out, int device, void* hip_stream);
+PW_API pw_status pw_ctx_destroy(pw_ctx ctx);
+
+/* Device bytes of workspace needed to evaluate up to `x_batch` families of an
+ * n-qubit state of the given dtype per launch, including the CDF used by the
+ * marginal sampler.  1 <= n <= 32. */
+PW_API pw_status pw_workspace_size(int n_qubits, pw_dtype dtype, int x_batch, size_t* bytes);
+
+/* Lend a device buffer (256-byte aligned) as workspace; the library carves all
+ * its scratch from it.  Pass NULL/0 to return to library-owned scratch. */
+PW_API pw_status pw_set_workspace(pw_ctx ctx, void* dev_ptr, size_t bytes);
+
+/* Bind a device state (2^n amplitudes, borrowed, 256-byte aligned).  Computes
+ * <psi|psi> in FP64 (one streaming read) and rejects NaN/Inf or a norm off by
+ * more than 1e-10 (PW_C128) / 1e-5 (PW_C64): the method assumes a normalised
+ * state (Pauli expansion paragraph).  norm2_out may be NULL. */
+PW_API pw_status pw_state_bind(pw_ctx ctx, int n_qubits, pw_dtype dtype, void* dev_psi, double* norm2_out);
+
+/* Copy a host state into the caller's device buffer dev_dst, then bind it. */
+PW_API pw_status pw_state_upload(pw_ctx ctx, int n_qubits, pw_dtype dtype, const void* host_psi,
+                          void* dev_dst, double* norm2_out);
+
+/* Apply a gate list to the bound state, in place, in order (Clifford
+ * preconditioning section: a random brick-wall Clifford circuit applied before
+ * sampling; also used to prepare T-doped circuit states).
+ *   kinds[g] = 2: dense 4x4 unitary on qubits (qubits[2g], qubits[2g+1]), acting on
+ *                 the local index b_{q0} + 2 b_{q1};
+ *   kinds[g] = 1: diagonal gate diag(d0, d1) on qubit qubits[2g].
+ *   mats: 16 complex doubles (interleaved) per gate, row-major; a diagonal gate
+ *         keeps (d0, d1) in its first two entries.
+ * Host arrays, copied before the call returns.  The state is not re-normalised. */
+PW_API pw_status pw_apply_gates(pw_ctx ctx, int n_gates, const int* kinds, const int* qubits, const double* mats);
+
+/* Evaluate the families of the host list xs[0..n_x) (any x < 2^n, repeats
+ * allowed) and write one pw_xres per x to the host array out.  eps is the
+ * nullity tolerance (the paper suggests 1e-7 in FP64; use >= 1e-4 with PW_C64). */
+PW_API pw_status pw_eval_x(pw_ctx ctx, const uint64_t* xs, int64_t n_x, double eps, pw_xres* out);
+
+/* Same, with device arrays, enqueued without synchronising (graph-capturable
+ * when a workspace is set). */
+PW_API pw_status pw_eval_x_device(pw_ctx ctx, const uint64_t* d_xs, int64_t n_x, double eps, pw_xres* d_out);
+
+/* The signed expectation values c(x, z) = (-i)^{|x&z|} F_x(z) of one family,
+ * z = 0..2^n-1, into the host array c (2^n doubles).  n <= 26. */
+PW_API pw_status pw_family_values(pw_ctx ctx, uint64_t x, double* c);
+
+/* Draw n x-strings on the device (Philox4x32-10 counters keyed by seed; sample i
+ * uses counter offset + i) into the host array xs_out.  Marginal sampling draws
+ * x = b1 ^ b2 with b1, b2 ~ |psi|^2 by inverse CDF and redraws x = 0 (at most
+ * 64 attempts; a sample still 0 is returned as 0). */
+PW_API pw_status pw_sample_x(pw_ctx ctx, pw_sampler sampler, uint64_t seed, uint64_t offset, int64_t n,
+                      uint64_t* xs_out);
+
+/* Exact enumeration of all 4^n Pauli strings (Algorithm 1): every x is
+ * evaluated; S_alpha, M_alpha, M_1, nu_cnt and the nullity are returned.
+ * Returns PW_ERR_TOLERANCE (with the result still written) when nu_cnt is not a
+ * power of two.  n <= 26. */
+PW_API pw_status pw_exact(pw_ctx ctx, double eps, pw_result* out);
+
+/* Monte Carlo estimate (Monte Carlo section).  x = 0 is always evaluated and
+ * counted; further x are drawn `batch` at a time from `sampler` and evaluated,
+ * until the standard error of M_2 is <= target_se (after at least 2 batches) or
+ * max_samples families have been evaluated.  The uniform sampler uses the
+ * paper's estimator S = m_0 + (d-1) mean(m_x); the marginal sampler uses
+ * S = m_0 + (1 - p(0)) mean(m_x / p(x)). */
+PW_API pw_status pw_mc(pw_ctx ctx, pw_sampler sampler, double eps, int batch, uint64_t max_samples,
+                double target_se, uint64_t seed, pw_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,567 @@
+// C ABI of libpauliwht (declared in include/pauliwht.h): contexts, workspace
+// carving, state binding, gate lists, per-family evaluation, exact enumeration
+// (Algorithm 1) and the Monte Carlo estimators (Monte Carlo section, Eq. stdM).
+#include "common.h"
+#include "pauliwht.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <string>
+#include <vector>
+
+using namespace pw;
+
+namespace {
+
+thread_local std::string g_err;
+
+pw_status fail(pw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+pw_status fail(pw_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+// Host-side fault injection for tests of the error paths: PW_FAULT=alloc|launch|copy
+// makes the named class of HIP call fail before it is issued.
+bool fault(const char* what) {
+    const char* f = getenv("PW_FAULT");
+    return f && strcmp(f, what) == 0;
+}
+
+#define PW_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(PW_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int MAX_QUBITS = 32;
+constexpr int EXACT_MAX_QUBITS = 26;
+constexpr int FAMILY_VALUES_MAX_QUBITS = 26;
+constexpr int SWEEP_SLOTS = 65536;   // batch sums kept before a second-level reduction
+constexpr int SWEEP_L2 = 4096;
+constexpr int MAX_BATCH = 4096;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t esize(pw_dtype dt) { return dt == PW_C128 ? 16 : 8; }
+
+// Workspace layout for (n, dtype, batch).
+struct Layout {
+    size_t work, parts, counters, xs, xres, sweep, cdf, cdfblk, norm, total;
+};
+
+Layout layout_for(int n, pw_dtype dt, int batch) {
+    const bool dbl = dt == PW_C128;
+    const Plan P = make_plan(n, dbl);
+    Layout L{};
+    const size_t half = (size_t)1 << (n - 1);
+    size_t work = P.fused ? 0 : (size_t)batch * half * esize(dt);
+    if (n <= FAMILY_VALUES_MAX_QUBITS) {
+        const size_t fam = align256(half * esize(dt)) + ((size_t)1 << n) * sizeof(double);
+        if (fam > work) work = fam;
+    }
+    size_t off = 0;
+    L.work = off;
+    off += align256(work);
+    L.parts = off;
+    off += align256((size_t)batch * (size_t)P.blocks_last * sizeof(FamilyRes));
+    L.counters = off;
+    off += align256((size_t)(batch + 1) * sizeof(unsigned));
+    L.xs = off;
+    off += align256((size_t)batch * sizeof(uint64_t));
+    L.xres = off;
+    off += align256((size_t)batch * sizeof(FamilyRes));
+    L.sweep = off;
+    off += align256((size_t)(SWEEP_SLOTS + SWEEP_L2 + 1) * sizeof(SweepSums));
+    L.cdf = off;
+    off += align256(((size_t)1 << n) * sizeof(double));
+    L.cdfblk = off;
+    off += align256(cdf_blk_elems(n) * sizeof(double));
+    L.norm = off;
+    off += align256((size_t)(norm2_parts(n) + 2) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int default_batch(int n, pw_dtype dt) {
+    const Plan P = make_plan(n, dt == PW_C128);
+    if (P.fused) return MAX_BATCH;
+    const size_t per = ((size_t)1 << (n - 1)) * esize(dt);
+    size_t b = ((size_t)256 << 20) / per;
+    if (b < 1) b = 1;
+    if (b > 256) b = 256;
+    // power of two
+    size_t p = 1;
+    while (p * 2 <= b) p *= 2;
+    return (int)p;
+}
+
+}  // namespace
+
+struct pw_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    // bound state
+    void* psi = nullptr;
+    int n = 0;
+    pw_dtype dtype = PW_C128;
+    bool bound = false;
+    int batch = 1;
+    Layout L{};
+    Plan P{};
+    bool cdf_valid = false;
+};
+
+namespace {
+
+pw_status check_ctx(pw_ctx c) {
+    if (!c) return fail(PW_ERR_ARG, "null context");
+    return PW_OK;
+}
+
+pw_status check_state(pw_ctx c) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (!c->bound) return fail(PW_ERR_NO_STATE, "no state bound to the context");
+    return PW_OK;
+}
+
+template <typename T>
+T* at(pw_ctx c, size_t off) {
+    return reinterpret_cast<T*>(c->ws + off);
+}
+
+// Carve (or allocate) the workspace for the bound state.
+pw_status prepare_workspace(pw_ctx c, int n, pw_dtype dt) {
+    if (c->ws && !c->ws_owned) {
+        int b = MAX_BATCH;
+        while (b >= 1 && layout_for(n, dt, b).total > c->ws_bytes) b /= 2;
+        if (b < 1)
+            return fail(PW_ERR_WORKSPACE, "workspace of %zu bytes is below the %zu needed for n=%d", c->ws_bytes,
+                        layout_for(n, dt, 1).total, n);
+        c->batch = b;
+    } else {
+        c->batch = default_batch(n, dt);
+        const size_t need = layout_for(n, dt, c->batch).total;
+        if (!c->ws || c->ws_bytes < need) {
+            if (c->ws) {
+                PW_HIP(hipStreamSynchronize(c->stream));
+                PW_HIP(hipFree(c->ws));
+                c->ws = nullptr;
+                c->ws_bytes = 0;
+            }
+            if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+            void* p = nullptr;
+            PW_HIP(hipMalloc(&p, need));
+            c->ws = (char*)p;
+            c->ws_bytes = need;
+            c->ws_owned = true;
+        }
+    }
+    c->L = layout_for(n, dt, c->batch);
+    c->P = make_plan(n, dt == PW_C128);
+    PW_HIP(hipMemsetAsync(c->ws + c->L.counters, 0, (size_t)(c->batch + 1) * sizeof(unsigned), c->stream));
+    return PW_OK;
+}
+
+pw_status run_norm(pw_ctx c, double* out) {
+    const int np = norm2_parts(c->n);
+    double* part = at<double>(c, c->L.norm);
+    double* res = part + np;
+    unsigned* bad = reinterpret_cast<unsigned*>(part + np + 1);
+    PW_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned), c->stream));
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    PW_HIP(norm2(c->dtype == PW_C128, c->psi, c->n, part, np, res, bad, c->stream));
+    double h[2];
+    PW_HIP(hipMemcpyAsync(h, res, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    unsigned hb;
+    memcpy(&hb, &h[1], sizeof hb);
+    if (hb) return fail(PW_ERR_NOT_NORMALIZED, "state holds NaN or Inf amplitudes");
+    *out = h[0];
+    return PW_OK;
+}
+
+// Evaluate nx families whose x are in device memory (or x0 + i when d_xs is null),
+// results to device array d_out.  Chunked by the context batch.
+pw_status eval_device(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out) {
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    const bool dbl = c->dtype == PW_C128;
+    for (int64_t i = 0; i < nx; i += c->batch) {
+        const int nb = (int)((nx - i) < c->batch ? (nx - i) : c->batch);
+        PW_HIP(eval_batch(c->P, dbl, c->psi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
+                          c->ws + c->L.work, at<FamilyRes>(c, c->L.parts), at<unsigned>(c, c->L.counters),
+                          d_out + i, nullptr, c->stream));
+    }
+    return PW_OK;
+}
+
+pw_status eval_host(pw_ctx c, const uint64_t* xs, int64_t nx, double eps, FamilyRes* out) {
+    uint64_t* dx = at<uint64_t>(c, c->L.xs);
+    FamilyRes* dr = at<FamilyRes>(c, c->L.xres);
+    for (int64_t i = 0; i < nx; i += c->batch) {
+        const int nb = (int)((nx - i) < c->batch ? (nx - i) : c->batch);
+        if (fault("copy")) return fail(PW_ERR_HIP, "hipMemcpy: injected failure (PW_FAULT=copy)");
+        PW_HIP(hipMemcpyAsync(dx, xs + i, nb * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+        pw_status s = eval_device(c, dx, 0, nb, eps, dr);
+        if (s != PW_OK) return s;
+        PW_HIP(hipMemcpyAsync(out + i, dr, nb * sizeof(FamilyRes), hipMemcpyDeviceToHost, c->stream));
+        PW_HIP(hipStreamSynchronize(c->stream));
+    }
+    return PW_OK;
+}
+
+bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+// Welford running mean / variance (fixed order, so reproducible).
+struct Running {
+    double n = 0, mean = 0, m2 = 0;
+    void add(double y) {
+        n += 1;
+        const double d = y - mean;
+        mean += d / n;
+        m2 += d * (y - mean);
+    }
+    double var() const { return n > 1 ? m2 / (n - 1) : NAN; }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* pw_last_error(void) { return g_err.c_str(); }
+
+const char* pw_version(void) { return "pauliwht 0.1 (gfx950)"; }
+
+pw_status pw_ctx_create(pw_ctx* out, int device, void* hip_stream) {
+    if (!out) return fail(PW_ERR_ARG, "null output pointer");
+    if (device < 0) return fail(PW_ERR_ARG, "negative device index");
+    PW_HIP(hipSetDevice(device));
+    pw_ctx c = new pw_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    g_err.clear();
+    return PW_OK;
+}
+
+pw_status pw_ctx_destroy(pw_ctx c) {
+    if (!c) return fail(PW_ERR_ARG, "null context");
+    pw_status s = PW_OK;
+    if (c->ws && c->ws_owned) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess || hipFree(c->ws) != hipSuccess)
+            s = fail(PW_ERR_HIP, "releasing the library-owned workspace failed");
+    }
+    delete c;
+    return s;
+}
+
+pw_status pw_workspace_size(int n, pw_dtype dt, int x_batch, size_t* bytes) {
+    if (!bytes) return fail(PW_ERR_ARG, "null output pointer");
+    if (dt != PW_C128 && dt != PW_C64) return fail(PW_ERR_ARG, "unknown dtype %d", (int)dt);
+    if (n < 1 || n > MAX_QUBITS) return fail(PW_ERR_RANGE, "n=%d outside [1, %d]", n, MAX_QUBITS);
+    if (x_batch < 1 || x_batch > MAX_BATCH) return fail(PW_ERR_RANGE, "x_batch=%d outside [1, %d]", x_batch, MAX_BATCH);
+    *bytes = layout_for(n, dt, x_batch).total;
+    return PW_OK;
+}
+
+pw_status pw_set_workspace(pw_ctx c, void* dev, size_t bytes) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (dev && ((uintptr_t)dev & 255)) return fail(PW_ERR_ARG, "workspace must be 256-byte aligned");
+    if (c->ws && c->ws_owned) {
+        PW_HIP(hipStreamSynchronize(c->stream));
+        PW_HIP(hipFree(c->ws));
+    }
+    c->ws = (char*)dev;
+    c->ws_bytes = dev ? bytes : 0;
+    c->ws_owned = false;
+    if (c->bound) {
+        c->bound = false;   // re-carve on the next bind
+        c->cdf_valid = false;
+        if (dev) {
+            s = prepare_workspace(c, c->n, c->dtype);
+            if (s != PW_OK) return s;
+            c->bound = true;
+        }
+    }
+    return PW_OK;
+}
+
+pw_status pw_state_bind(pw_ctx c, int n, pw_dtype dt, void* dev_psi, double* norm2_out) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (!dev_psi) return fail(PW_ERR_ARG, "null state pointer");
+    if ((uintptr_t)dev_psi & 255) return fail(PW_ERR_ARG, "state must be 256-byte aligned");
+    if (dt != PW_C128 && dt != PW_C64) return fail(PW_ERR_ARG, "unknown dtype %d", (int)dt);
+    if (n < 1 || n > MAX_QUBITS) return fail(PW_ERR_RANGE, "n=%d outside [1, %d]", n, MAX_QUBITS);
+    c->bound = false;
+    c->cdf_valid = false;
+    c->psi = dev_psi;
+    c->n = n;
+    c->dtype = dt;
+    s = prepare_workspace(c, n, dt);
+    if (s != PW_OK) return s;
+    double nrm = 0.0;
+    s = run_norm(c, &nrm);
+    if (s != PW_OK) return s;
+    const double tol = dt == PW_C128 ? 1e-10 : 1e-5;
+    if (!(fabs(nrm - 1.0) <= tol))
+        return fail(PW_ERR_NOT_NORMALIZED, "<psi|psi> = %.17g differs from 1 by more than %g", nrm, tol);
+    c->bound = true;
+    if (norm2_out) *norm2_out = nrm;
+    return PW_OK;
+}
+
+pw_status pw_state_upload(pw_ctx c, int n, pw_dtype dt, const void* host_psi, void* dev_dst, double* norm2_out) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (!host_psi || !dev_dst) return fail(PW_ERR_ARG, "null pointer");
+    if (dt != PW_C128 && dt != PW_C64) return fail(PW_ERR_ARG, "unknown dtype %d", (int)dt);
+    if (n < 1 || n > MAX_QUBITS) return fail(PW_ERR_RANGE, "n=%d outside [1, %d]", n, MAX_QUBITS);
+    if (fault("copy")) return fail(PW_ERR_HIP, "hipMemcpy: injected failure (PW_FAULT=copy)");
+    PW_HIP(hipMemcpyAsync(dev_dst, host_psi, ((size_t)1 << n) * esize(dt), hipMemcpyHostToDevice, c->stream));
+    return pw_state_bind(c, n, dt, dev_dst, norm2_out);
+}
+
+pw_status pw_apply_gates(pw_ctx c, int ng, const int* kinds, const int* qubits, const double* mats) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (ng < 0) return fail(PW_ERR_ARG, "negative gate count");
+    if (ng > 0 && (!kinds || !qubits || !mats)) return fail(PW_ERR_ARG, "null gate array");
+    for (int g = 0; g < ng; ++g) {
+        const int q0 = qubits[2 * g], q1 = qubits[2 * g + 1];
+        if (kinds[g] == 2) {
+            if (c->n < 2 || q0 < 0 || q1 < 0 || q0 >= c->n || q1 >= c->n || q0 == q1)
+                return fail(PW_ERR_RANGE, "gate %d: qubits (%d, %d) invalid for n=%d", g, q0, q1, c->n);
+        } else if (kinds[g] == 1) {
+            if (q0 < 0 || q0 >= c->n) return fail(PW_ERR_RANGE, "gate %d: qubit %d invalid for n=%d", g, q0, c->n);
+        } else {
+            return fail(PW_ERR_ARG, "gate %d: unknown kind %d", g, kinds[g]);
+        }
+    }
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    const bool dbl = c->dtype == PW_C128;
+    for (int g = 0; g < ng; ++g) {
+        if (kinds[g] == 2) PW_HIP(apply_gate2(dbl, c->psi, c->n, qubits[2 * g], qubits[2 * g + 1], mats + 32 * g, c->stream));
+        else PW_HIP(apply_diag(dbl, c->psi, c->n, qubits[2 * g], mats + 32 * g, c->stream));
+    }
+    c->cdf_valid = false;
+    PW_HIP(hipStreamSynchronize(c->stream));
+    return PW_OK;
+}
+
+pw_status pw_eval_x(pw_ctx c, const uint64_t* xs, int64_t nx, double eps, pw_xres* out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (nx < 0) return fail(PW_ERR_ARG, "negative count");
+    if (nx > 0 && (!xs || !out)) return fail(PW_ERR_ARG, "null array");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
+    const uint64_t d = 1ull << c->n;
+    for (int64_t i = 0; i < nx; ++i)
+        if (xs[i] >= d) return fail(PW_ERR_RANGE, "xs[%lld] = %llu is not below 2^%d", (long long)i, (unsigned long long)xs[i], c->n);
+    std::vector<FamilyRes> tmp((size_t)nx);
+    s = eval_host(c, xs, nx, eps, tmp.data());
+    if (s != PW_OK) return s;
+    memcpy(out, tmp.data(), (size_t)nx * sizeof(FamilyRes));
+    return PW_OK;
+}
+
+pw_status pw_eval_x_device(pw_ctx c, const uint64_t* d_xs, int64_t nx, double eps, pw_xres* d_out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (nx < 0) return fail(PW_ERR_ARG, "negative count");
+    if (nx > 0 && (!d_xs || !d_out)) return fail(PW_ERR_ARG, "null array");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
+    return eval_device(c, d_xs, 0, nx, eps, reinterpret_cast<FamilyRes*>(d_out));
+}
+
+pw_status pw_family_values(pw_ctx c, uint64_t x, double* cvals) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (!cvals) return fail(PW_ERR_ARG, "null output");
+    if (c->n > FAMILY_VALUES_MAX_QUBITS) return fail(PW_ERR_RANGE, "family values limited to n <= %d", FAMILY_VALUES_MAX_QUBITS);
+    if (x >= (1ull << c->n)) return fail(PW_ERR_RANGE, "x not below 2^n");
+    if (c->n < 14) return fail(PW_ERR_UNSUPPORTED, "family values need n >= 14 (multi-pass transform)");
+    const bool dbl = c->dtype == PW_C128;
+    void* G = c->ws + c->L.work;
+    double* cv = reinterpret_cast<double*>(c->ws + c->L.work + align256(((size_t)1 << (c->n - 1)) * esize(c->dtype)));
+    Plan P = make_plan(c->n, dbl);
+    if (P.fused) return fail(PW_ERR_UNSUPPORTED, "family values need the multi-pass transform");
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    PW_HIP(transform_one(P, dbl, c->psi, x, G, c->stream));
+    PW_HIP(signed_values(P, dbl, G, x, cv, c->stream));
+    PW_HIP(hipMemcpyAsync(cvals, cv, ((size_t)1 << c->n) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    return PW_OK;
+}
+
+pw_status pw_sample_x(pw_ctx c, pw_sampler sampler, uint64_t seed, uint64_t offset, int64_t n, uint64_t* xs_out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (n < 0) return fail(PW_ERR_ARG, "negative count");
+    if (n > 0 && !xs_out) return fail(PW_ERR_ARG, "null output");
+    if (sampler != PW_SAMPLER_UNIFORM_NZ && sampler != PW_SAMPLER_MARGINAL_NZ) return fail(PW_ERR_ARG, "unknown sampler");
+    if (c->n < 1) return fail(PW_ERR_RANGE, "need n >= 1");
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    uint64_t* dx = at<uint64_t>(c, c->L.xs);
+    if (sampler == PW_SAMPLER_MARGINAL_NZ && !c->cdf_valid) {
+        PW_HIP(build_cdf(c->dtype == PW_C128, c->psi, c->n, at<double>(c, c->L.cdf), at<double>(c, c->L.cdfblk), c->stream));
+        c->cdf_valid = true;
+    }
+    for (int64_t i = 0; i < n; i += c->batch) {
+        const int64_t nb = (n - i) < c->batch ? (n - i) : c->batch;
+        if (sampler == PW_SAMPLER_UNIFORM_NZ) PW_HIP(sample_uniform(c->n, seed, offset + (uint64_t)i, nb, dx, c->stream));
+        else PW_HIP(sample_marginal(c->n, at<double>(c, c->L.cdf), seed, offset + (uint64_t)i, nb, dx, c->stream));
+        PW_HIP(hipMemcpyAsync(xs_out + i, dx, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+        PW_HIP(hipStreamSynchronize(c->stream));
+    }
+    return PW_OK;
+}
+
+pw_status pw_exact(pw_ctx c, double eps, pw_result* out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (!out) return fail(PW_ERR_ARG, "null output");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
+    if (c->n > EXACT_MAX_QUBITS) return fail(PW_ERR_RANGE, "exact enumeration limited to n <= %d", EXACT_MAX_QUBITS);
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    const bool dbl = c->dtype == PW_C128;
+    const uint64_t d = 1ull << c->n;
+    SweepSums* sw = at<SweepSums>(c, c->L.sweep);
+    SweepSums* l2 = sw + SWEEP_SLOTS;
+    SweepSums* fin = l2 + SWEEP_L2;
+    FamilyRes* xr = at<FamilyRes>(c, c->L.xres);
+    int64_t nbatch = 0, nl2 = 0;
+    for (uint64_t x0 = 0; x0 < d; x0 += (uint64_t)c->batch) {
+        const int nb = (int)((d - x0) < (uint64_t)c->batch ? (d - x0) : (uint64_t)c->batch);
+        PW_HIP(eval_batch(c->P, dbl, c->psi, nullptr, x0, nb, eps, c->ws + c->L.work, at<FamilyRes>(c, c->L.parts),
+                          at<unsigned>(c, c->L.counters), xr, sw + nbatch, c->stream));
+        if (++nbatch == SWEEP_SLOTS) {
+            if (nl2 == SWEEP_L2) return fail(PW_ERR_UNSUPPORTED, "too many batches");
+            PW_HIP(reduce_sweep(sw, nbatch, l2 + nl2, c->stream));
+            ++nl2;
+            nbatch = 0;
+        }
+    }
+    if (nbatch > 0) {
+        PW_HIP(reduce_sweep(sw, nbatch, l2 + nl2, c->stream));
+        ++nl2;
+    }
+    PW_HIP(reduce_sweep(l2, nl2, fin, c->stream));
+    SweepSums h;
+    PW_HIP(hipMemcpyAsync(&h, fin, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    pw_result r;
+    memset(&r, 0, sizeof r);
+    const int n = c->n;
+    for (int a = 0; a < 3; ++a) {
+        r.S[a] = h.S[a];
+        r.S_se[a] = 0.0;
+        r.M[a] = log2(h.S[a]) / (1.0 - (a + 2)) - n;
+        r.M_se[a] = 0.0;
+        r.r[a] = NAN;
+    }
+    r.L = h.L;
+    r.L_se = 0.0;
+    r.M1 = -ldexp(h.L, -n);
+    r.M1_se = 0.0;
+    r.P = h.P;
+    r.nu_cnt = h.nu_cnt;
+    r.nullity = h.nu_cnt ? n - log2((double)h.nu_cnt) : NAN;
+    r.n_samples = h.count;
+    r.gap = h.gap;
+    *out = r;
+    if (!is_pow2(h.nu_cnt))
+        return fail(PW_ERR_TOLERANCE, "nullity count %llu is not a power of two (gap %.3g): eps does not separate |c| = 1",
+                    (unsigned long long)h.nu_cnt, h.gap);
+    return PW_OK;
+}
+
+pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t max_samples, double target_se,
+                uint64_t seed, pw_result* out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (!out) return fail(PW_ERR_ARG, "null output");
+    if (sampler != PW_SAMPLER_UNIFORM_NZ && sampler != PW_SAMPLER_MARGINAL_NZ) return fail(PW_ERR_ARG, "unknown sampler");
+    if (batch < 1) return fail(PW_ERR_ARG, "batch must be >= 1");
+    if (max_samples < 3) return fail(PW_ERR_ARG, "max_samples must be >= 3");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
+    const int n = c->n;
+    const double d = ldexp(1.0, n);
+    // x = 0 is always evaluated (Monte Carlo section).
+    FamilyRes r0;
+    const uint64_t zero = 0;
+    s = eval_host(c, &zero, 1, eps, &r0);
+    if (s != PW_OK) return s;
+    const double p0 = r0.p;
+    if (sampler == PW_SAMPLER_MARGINAL_NZ && !(p0 < 1.0 - 1e-12))
+        return fail(PW_ERR_UNSUPPORTED, "p(0) = %.17g: the x-marginal has no mass on x != 0", p0);
+    Running run[4];   // alpha = 2, 3, 4 and the Shannon term
+    double gap = r0.gap;
+    uint64_t drawn = 0;
+    std::vector<uint64_t> xs;
+    std::vector<FamilyRes> res;
+    const uint64_t draws_max = max_samples - 1;
+    int batches = 0;
+    while (drawn < draws_max) {
+        const int64_t nb = (int64_t)((draws_max - drawn) < (uint64_t)batch ? (draws_max - drawn) : (uint64_t)batch);
+        xs.resize((size_t)nb);
+        res.resize((size_t)nb);
+        s = pw_sample_x(c, sampler, seed, drawn, nb, xs.data());
+        if (s != PW_OK) return s;
+        for (int64_t i = 0; i < nb; ++i)
+            if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
+        s = eval_host(c, xs.data(), nb, eps, res.data());
+        if (s != PW_OK) return s;
+        for (int64_t i = 0; i < nb; ++i) {
+            const FamilyRes& f = res[i];
+            const double w = sampler == PW_SAMPLER_UNIFORM_NZ ? (d - 1.0) : (1.0 - p0) / f.p;
+            for (int a = 0; a < 3; ++a) run[a].add(w * f.m[a]);
+            run[3].add(w * f.ent);
+            gap = fmax(gap, f.gap);
+        }
+        drawn += (uint64_t)nb;
+        ++batches;
+        const double S2 = r0.m[0] + run[0].mean;
+        const double se2 = sqrt(run[0].var() / run[0].n);
+        const double Mse = se2 / (log(2.0) * S2);
+        if (batches >= 2 && target_se > 0 && Mse <= target_se) break;
+    }
+    pw_result r;
+    memset(&r, 0, sizeof r);
+    for (int a = 0; a < 3; ++a) {
+        const double S = r0.m[a] + run[a].mean;
+        const double se = sqrt(run[a].var() / run[a].n);
+        r.S[a] = S;
+        r.S_se[a] = se;
+        r.M[a] = log2(S) / (1.0 - (a + 2)) - n;
+        r.M_se[a] = se / (fabs(1.0 - (a + 2)) * log(2.0) * S);
+        r.r[a] = sqrt(run[a].var()) / S;
+    }
+    r.L = r0.ent + run[3].mean;
+    r.L_se = sqrt(run[3].var() / run[3].n);
+    r.M1 = -r.L / d;
+    r.M1_se = r.L_se / d;
+    r.P = NAN;
+    r.nullity = NAN;
+    r.nu_cnt = 0;
+    r.n_samples = drawn + 1;
+    r.gap = gap;
+    *out = r;
+    return PW_OK;
+}
+
+}  // extern "C"

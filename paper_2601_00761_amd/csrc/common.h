@@ -1,0 +1,85 @@
+// Internal declarations shared by the HIP translation units of libpauliwht.
+// Not part of the public C ABI (that is include/pauliwht.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace pw {
+
+template <typename R>
+struct __align__(2 * sizeof(R)) cx {
+    R re, im;
+};
+
+// Per-family accumulators, FP64.  One per workgroup of the final transform pass,
+// then one per family after the fixed-order finalize.  Layout matches pw_xres
+// from the public header (x, p, ent, m[3], gap, nu).
+struct FamilyRes {
+    uint64_t x;
+    double p;       // sum |F|^2 (scaled by 2^-n at finalize)
+    double ent;     // sum |F|^2 log2 |F|^2
+    double m[3];    // sum |F|^{2a}, a = 2, 3, 4 (scaled by 2^-na at finalize)
+    double gap;     // max |F| below 1 - eps, -1 if none
+    uint64_t nu;    // count of ||F| - 1| < eps
+};
+static_assert(sizeof(FamilyRes) == 64, "FamilyRes layout");
+
+// Sums over a set of families (exact sweep, batch level).
+struct SweepSums {
+    double S[3];
+    double L;
+    double P;
+    double gap;
+    uint64_t nu_cnt;
+    uint64_t count;
+};
+static_assert(sizeof(SweepSums) == 64, "SweepSums layout");
+
+// The pass schedule of one transform of 2^nh points (nh = n - 1 after the
+// Hermitian halving): a first tile pass over bits [0, k1) that also forms the
+// products, then column passes over [lo_i, lo_i + s_i).
+struct Plan {
+    int n;          // qubits
+    int nh;         // transform bits = n - 1 (n >= 2)
+    bool fused;     // whole transform inside one workgroup (nh <= small limit)
+    int k1;         // bits of the first pass
+    int npass;      // number of column passes after the first
+    int lo[4];
+    int s[4];
+    int blocks_last;   // workgroups per family in the final pass
+};
+
+Plan make_plan(int n, bool dbl);
+
+// Launchers (host side, enqueue on `st`).  All return hipSuccess or the first error.
+// Evaluate a batch of nb families.  If xs != nullptr the x of slot i is xs[i],
+// else it is x0 + i.  Per-family results go to out[i].  If batch_sum != nullptr
+// the fixed-order sum of the batch is also written there.
+hipError_t eval_batch(const Plan& P, bool dbl, const void* psi, const uint64_t* xs, uint64_t x0, int nb,
+                      double eps, void* work, FamilyRes* parts, unsigned* counters, FamilyRes* out,
+                      SweepSums* batch_sum, hipStream_t st);
+
+// Transform only (no reductions): writes the 2^nh half-spectrum G of one x into work.
+hipError_t transform_one(const Plan& P, bool dbl, const void* psi, uint64_t x, void* work, hipStream_t st);
+// Signed values c(x, z) from the half spectrum G (2^n doubles).
+hipError_t signed_values(const Plan& P, bool dbl, const void* G, uint64_t x, double* c, hipStream_t st);
+
+// Sum an array of batch sums (fixed order) into one.
+hipError_t reduce_sweep(const SweepSums* in, int64_t count, SweepSums* out, hipStream_t st);
+
+// State helpers.
+hipError_t norm2(bool dbl, const void* psi, int n, double* d_partial, int nparts, double* d_out, unsigned* d_bad,
+                 hipStream_t st);
+int norm2_parts(int n);
+hipError_t apply_gate2(bool dbl, void* psi, int n, int q0, int q1, const double* m16 /*host*/, hipStream_t st);
+hipError_t apply_diag(bool dbl, void* psi, int n, int q, const double* d2 /*host*/, hipStream_t st);
+
+// Sampling.
+hipError_t sample_uniform(int n, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs, hipStream_t st);
+hipError_t build_cdf(bool dbl, const void* psi, int n, double* d_cdf, double* d_blk, hipStream_t st);
+size_t cdf_blk_elems(int n);
+hipError_t sample_marginal(int n, const double* d_cdf, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs,
+                           hipStream_t st);
+
+}  // namespace pw
