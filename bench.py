@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the FWHT Pauli-string path on one MI355X.
+
+Workload: an N = 20 T-doped random Clifford state (|0...0> followed by uniformly
+random two-qubit Cliffords in brick-wall order with eta = 20 Cliffords per T gate and
+N_T = 20 T gates on random qubits), and exact enumeration of all 4^20 Pauli
+strings: every X-bitstring x is evaluated (product, transform over all 2^20 z,
+moments, Shannon term, nullity count), then S_alpha, M_1, M_alpha and the nullity
+are formed.  One step is one full enumeration (2^40 Pauli strings).  The main
+leg runs the transform in FP32 on a complex64 state; a second leg times the FP64
+path on the complex128 state.
+
+Prints one JSON line.  The input lives in HBM before the timed region; the state
+is prepared on the GPU by the library's gate kernels (input generation, untimed).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_QUBITS = 20
+ETA = 20
+N_T = 20
+HBM_PEAK_GBS = 8000.0
+KCLASS = {0: "k_fused", 1: "k_first", 2: "k_column(mid)", 3: "k_column(last)"}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fwht.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2601_00761_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, dtype_tag):
+    """HBM traffic per launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_%s_n20.json" % dtype_tag)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def prepare_state(pw, torch, n, seed):
+    import numpy as np
+    import synth
+    gates = synth.tdoped_stream(n, ETA, N_T, seed)
+    kinds, qubits, mats = synth.gates_to_arrays(gates)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1.0
+    return psi0, (kinds, qubits, mats)
+
+
+def cpu_baseline(psi128, budget_s):
+    """The FP64 oracle (Algorithm 1 per family) on a bounded sample of the same
+    enumeration: families x = 0, 1, 2, ... until budget_s seconds of host time."""
+    import numpy as np
+    import oracle
+    n = int(round(math.log2(len(psi128))))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    done = 0
+    t0 = time.perf_counter()
+    chunk = 4
+    while True:
+        xs = np.arange(done, done + chunk, dtype=np.uint64)
+        oracle.eval_x(psi128, xs, eps=1e-7, max_alpha=4)
+        done += chunk
+        el = time.perf_counter() - t0
+        if el >= budget_s or done >= (1 << n):
+            break
+    el = time.perf_counter() - t0
+    return {"value": done * float(1 << n) / el, "unit": "Pauli strings/s", "cores": threads, "kind": "oracle",
+            "sample": "families x = 0..%d of the N=%d enumeration (%d of %d families, %.1f s, FP64 Algorithm 1 "
+                      "with OpenMP inside each transform stage)" % (done - 1, n, done, 1 << n, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps-c128", type=int, default=2)
+    ap.add_argument("--timing-every", type=int, default=16, help="time every k-th launch of each kernel class")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-alpha", type=int, default=2, choices=(2, 4),
+                    help="moments computed per family (the workload asks for M_1, M_2 and the nullity)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the method shards over x; see "
+              "DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2601_00761_amd as pw
+    import synth
+
+    n = N_QUBITS
+    seed = synth.SEED_BASE + 2
+    psi0, gates = prepare_state(pw, torch, n, seed)
+
+    stream = torch.cuda.current_stream(0)
+    # state preparation on the GPU in FP64, then a complex64 copy for the main leg
+    prep = pw.Context(0, stream)
+    prep.upload(psi0, pw.PW_C128)
+    prep.apply_gates(*gates)
+    psi128_dev = prep.psi
+    psi64_dev = psi128_dev.to(torch.complex64)
+    torch.cuda.synchronize()
+
+    results = {}
+
+    def leg(dtype, psi_dev, steps, warmup, eps, timing):
+        ctx = pw.Context(0, stream)
+        pw.pw_set_moments(ctx.h, args.max_alpha)
+        ctx.bind(psi_dev, dtype)
+        for _ in range(warmup):
+            ctx.exact(eps)
+        if timing:
+            pw.pw_timing_enable(ctx.h, args.timing_every)
+            pw.pw_timing_reset(ctx.h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(steps):
+            last = ctx.exact(eps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = {}
+        if timing:
+            for k in range(4):
+                cnt, ms, fam = pw.pw_timing_read(ctx.h, k)
+                if cnt:
+                    kt[k] = dict(samples=cnt, avg_ms=ms / cnt, families_per_launch=fam / cnt)
+            pw.pw_timing_enable(ctx.h, 0)
+        batch = ctx_batch = None
+        ctx.close()
+        return el, last, kt
+
+    el64, r64, kt64 = leg(pw.PW_C64, psi64_dev, args.steps, args.warmup, 1e-4, True)
+    strings = float(1 << n) ** 2
+    value = args.steps * strings / el64
+
+    # dominant kernel = largest share of the sampled time per family
+    dom = max(kt64, key=lambda k: kt64[k]["avg_ms"] / kt64[k]["families_per_launch"])
+    d = kt64[dom]
+    alg_bytes = d["families_per_launch"] * float(1 << n) * 8.0       # one read of psi per family (complex64)
+    achieved = alg_bytes / (d["avg_ms"] * 1e-3) / 1e9
+    traffic = load_traffic(KCLASS[dom], "c64")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": KCLASS[dom],
+                "kernel_avg_us": round(d["avg_ms"] * 1e3, 2), "families_per_launch": d["families_per_launch"],
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "per_class_avg_us": {KCLASS[k]: round(v["avg_ms"] * 1e3, 2) for k, v in kt64.items()}}
+
+    el128 = r128 = None
+    if args.steps_c128 > 0:
+        el128, r128, _ = leg(pw.PW_C128, psi128_dev, args.steps_c128, 1, 1e-7, False)
+
+    out = {
+        "metric": "Pauli strings evaluated/sec (FWHT path)",
+        "value": value,
+        "unit": "Pauli strings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "exact enumeration of all 4^20 Pauli strings of an N=20 T-doped random Clifford "
+                               "state (eta=20, N_T=20, from |0..0>), complex64 state, FP32 transform, FP64 sums",
+                   "n_qubits": n, "eta": ETA, "n_t": N_T, "seed": seed, "families_per_step": 1 << n,
+                   "outputs": "M_1, M_2, nullity" if args.max_alpha == 2 else "M_1, M_2, M_3, M_4, nullity",
+                   "pauli_strings_per_step": strings, "parallelism": "single GPU"},
+        "results_c64": {"M1": r64["M1"], "M2": r64["M"][0], "M3": r64["M"][1], "M4": r64["M"][2],
+                        "nullity": r64["nullity"], "P": r64["P"]},
+        "roofline": roofline,
+    }
+    if r128 is not None:
+        out["c128"] = {"value": args.steps_c128 * strings / el128, "ms_per_step": 1e3 * el128 / args.steps_c128,
+                       "dtype": "f64", "M1": r128["M1"], "M2": r128["M"][0], "nullity": r128["nullity"],
+                       "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0]}
+    if not args.no_cpu_baseline:
+        import oracle
+        psi_host = psi128_dev.cpu().numpy()
+        # the oracle prepares its own copy of the state from the same gate list
+        psi_oracle = oracle.apply_gates(psi0, *gates)
+        out["cpu_baseline"] = cpu_baseline(psi_oracle, args.cpu_budget)
+        out["cpu_baseline"]["state_check_max_abs_diff"] = float(np.max(np.abs(psi_host - psi_oracle)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,6 +180,23 @@ PW_API pw_status pw_exact(pw_ctx ctx, double eps, pw_result* out);
 PW_API pw_status pw_mc(pw_ctx ctx, pw_sampler sampler, double eps, int batch, uint64_t max_samples,
                 double target_se, uint64_t seed, pw_result* out);
 
+/* Highest moment order computed per family: 4 (default: alpha = 2, 3, 4) or 2
+ * (alpha = 2 only; m[1], m[2], S[1], S[2], M[1], M[2] are then NaN).  M_1, p(x)
+ * and the nullity count are always computed. */
+PW_API pw_status pw_set_moments(pw_ctx ctx, int max_alpha);
+
+/* Measurement support.  pw_timing_enable(ctx, k) records a pair of HIP events on
+ * the context stream around every k-th launch of each kernel class (k = 0
+ * disables): class 0 = single-workgroup family kernel (small n), 1 = first
+ * transform pass (products + low 12 index bits), 2 = middle column pass,
+ * 3 = final column pass with the reductions.  pw_timing_read synchronises the
+ * recorded events and returns, for one class, the number of timed launches,
+ * their summed duration in milliseconds and the families they processed.
+ * pw_timing_reset clears the accumulators. */
+PW_API pw_status pw_timing_enable(pw_ctx ctx, int every);
+PW_API pw_status pw_timing_read(pw_ctx ctx, int kclass, uint64_t* samples, double* total_ms, uint64_t* families);
+PW_API pw_status pw_timing_reset(pw_ctx ctx);
+
 #ifdef __cplusplus
 }
 #endif

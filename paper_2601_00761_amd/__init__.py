@@ -20,7 +20,8 @@ __all__ = [
     "PWError", "PW_C128", "PW_C64", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "lib_path", "Context",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
+    "Context",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -96,6 +97,10 @@ def _load():
         "pw_sample_x": ([_vp, _int, _u64, _u64, _i64, _vp], _int),
         "pw_exact": ([_vp, _dbl, ctypes.POINTER(pw_result)], _int),
         "pw_mc": ([_vp, _int, _dbl, _int, _u64, _dbl, _u64, ctypes.POINTER(pw_result)], _int),
+        "pw_set_moments": ([_vp, _int], _int),
+        "pw_timing_enable": ([_vp, _int], _int),
+        "pw_timing_read": ([_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(_dbl), ctypes.POINTER(_u64)], _int),
+        "pw_timing_reset": ([_vp], _int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -216,6 +221,26 @@ def pw_mc(ctx, sampler, eps, batch, max_samples, target_se, seed):
     _check(_L.pw_mc(ctx, int(sampler), float(eps), int(batch), int(max_samples), float(target_se), int(seed),
                     ctypes.byref(r)))
     return r.as_dict()
+
+
+def pw_set_moments(ctx, max_alpha):
+    _check(_L.pw_set_moments(ctx, int(max_alpha)))
+
+
+def pw_timing_enable(ctx, every):
+    _check(_L.pw_timing_enable(ctx, int(every)))
+
+
+def pw_timing_read(ctx, kclass):
+    """(timed launches, summed milliseconds, families processed by them) for one kernel class."""
+    n, f = _u64(), _u64()
+    ms = _dbl()
+    _check(_L.pw_timing_read(ctx, int(kclass), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(f)))
+    return n.value, ms.value, f.value
+
+
+def pw_timing_reset(ctx):
+    _check(_L.pw_timing_reset(ctx))
 
 
 class Context:

@@ -45,8 +45,8 @@ bool fault(const char* what) {
 constexpr int MAX_QUBITS = 32;
 constexpr int EXACT_MAX_QUBITS = 26;
 constexpr int FAMILY_VALUES_MAX_QUBITS = 26;
-constexpr int SWEEP_SLOTS = 65536;   // batch sums kept before a second-level reduction
-constexpr int SWEEP_L2 = 4096;
+constexpr int SWEEP_SLOTS = 4096;    // per-chunk sums of an exact sweep
+constexpr int64_t EXACT_CHUNK = 1 << 20;  // families per chunk of an exact sweep
 constexpr int MAX_BATCH = 4096;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -55,7 +55,7 @@ size_t esize(pw_dtype dt) { return dt == PW_C128 ? 16 : 8; }
 
 // Workspace layout for (n, dtype, batch).
 struct Layout {
-    size_t work, parts, counters, xs, xres, sweep, cdf, cdfblk, norm, total;
+    size_t work, parts, xs, xres, fam, sweep, cdf, cdfblk, norm, total;
 };
 
 Layout layout_for(int n, pw_dtype dt, int batch) {
@@ -73,14 +73,15 @@ Layout layout_for(int n, pw_dtype dt, int batch) {
     off += align256(work);
     L.parts = off;
     off += align256((size_t)batch * (size_t)P.blocks_last * sizeof(FamilyRes));
-    L.counters = off;
-    off += align256((size_t)(batch + 1) * sizeof(unsigned));
     L.xs = off;
     off += align256((size_t)batch * sizeof(uint64_t));
     L.xres = off;
     off += align256((size_t)batch * sizeof(FamilyRes));
+    L.fam = off;
+    const int64_t chunk = ((int64_t)1 << n) < EXACT_CHUNK ? ((int64_t)1 << n) : EXACT_CHUNK;
+    off += align256((size_t)chunk * sizeof(FamilyRes));
     L.sweep = off;
-    off += align256((size_t)(SWEEP_SLOTS + SWEEP_L2 + 1) * sizeof(SweepSums));
+    off += align256((size_t)(SWEEP_SLOTS + 1) * sizeof(SweepSums));
     L.cdf = off;
     off += align256(((size_t)1 << n) * sizeof(double));
     L.cdfblk = off;
@@ -122,9 +123,68 @@ struct pw_ctx_s {
     Layout L{};
     Plan P{};
     bool cdf_valid = false;
+    int max_alpha = 4;
+    // launch timing (measurement)
+    int timing_every = 0;
+    uint64_t launches[4] = {0, 0, 0, 0};
+    struct Pair {
+        hipEvent_t a, b;
+        int kclass, families;
+    };
+    bool active[4] = {false, false, false, false};
+    hipEvent_t open_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<Pair> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[4] = {0, 0, 0, 0};
+    uint64_t samples[4] = {0, 0, 0, 0};
+    uint64_t sampled_families[4] = {0, 0, 0, 0};
+    LaunchTimer timer{};
 };
 
 namespace {
+
+hipEvent_t take_event(pw_ctx c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void timer_begin(void* self, int k, hipStream_t st) {
+    pw_ctx c = (pw_ctx)self;
+    if (c->launches[k]++ % (uint64_t)c->timing_every != 0) return;
+    hipEvent_t a = take_event(c);
+    if (!a) return;
+    if (hipEventRecord(a, st) != hipSuccess) {
+        c->pool.push_back(a);
+        return;
+    }
+    c->open_ev[k] = a;
+    c->active[k] = true;
+}
+
+void timer_end(void* self, int k, int families, hipStream_t st) {
+    pw_ctx c = (pw_ctx)self;
+    if (!c->active[k]) return;
+    c->active[k] = false;
+    hipEvent_t b = take_event(c);
+    if (!b) {
+        c->pool.push_back(c->open_ev[k]);
+        return;
+    }
+    if (hipEventRecord(b, st) != hipSuccess) {
+        c->pool.push_back(c->open_ev[k]);
+        c->pool.push_back(b);
+        return;
+    }
+    c->pending.push_back({c->open_ev[k], b, k, families});
+}
+
+const LaunchTimer* timer_of(pw_ctx c) { return c->timing_every > 0 ? &c->timer : nullptr; }
 
 pw_status check_ctx(pw_ctx c) {
     if (!c) return fail(PW_ERR_ARG, "null context");
@@ -172,7 +232,6 @@ pw_status prepare_workspace(pw_ctx c, int n, pw_dtype dt) {
     }
     c->L = layout_for(n, dt, c->batch);
     c->P = make_plan(n, dt == PW_C128);
-    PW_HIP(hipMemsetAsync(c->ws + c->L.counters, 0, (size_t)(c->batch + 1) * sizeof(unsigned), c->stream));
     return PW_OK;
 }
 
@@ -201,9 +260,8 @@ pw_status eval_device(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, d
     const bool dbl = c->dtype == PW_C128;
     for (int64_t i = 0; i < nx; i += c->batch) {
         const int nb = (int)((nx - i) < c->batch ? (nx - i) : c->batch);
-        PW_HIP(eval_batch(c->P, dbl, c->psi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
-                          c->ws + c->L.work, at<FamilyRes>(c, c->L.parts), at<unsigned>(c, c->L.counters),
-                          d_out + i, nullptr, c->stream));
+        PW_HIP(eval_batch(c->P, dbl, c->max_alpha, c->psi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
+                          c->ws + c->L.work, at<FamilyRes>(c, c->L.parts), d_out + i, c->stream, timer_of(c)));
     }
     return PW_OK;
 }
@@ -252,6 +310,9 @@ pw_status pw_ctx_create(pw_ctx* out, int device, void* hip_stream) {
     pw_ctx c = new pw_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    c->timer.begin = timer_begin;
+    c->timer.end = timer_end;
+    c->timer.self = c;
     *out = c;
     g_err.clear();
     return PW_OK;
@@ -260,6 +321,12 @@ pw_status pw_ctx_create(pw_ctx* out, int device, void* hip_stream) {
 pw_status pw_ctx_destroy(pw_ctx c) {
     if (!c) return fail(PW_ERR_ARG, "null context");
     pw_status s = PW_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->ws && c->ws_owned) {
         if (hipStreamSynchronize(c->stream) != hipSuccess || hipFree(c->ws) != hipSuccess)
             s = fail(PW_ERR_HIP, "releasing the library-owned workspace failed");
@@ -438,29 +505,20 @@ pw_status pw_exact(pw_ctx c, double eps, pw_result* out) {
     if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
     if (c->n > EXACT_MAX_QUBITS) return fail(PW_ERR_RANGE, "exact enumeration limited to n <= %d", EXACT_MAX_QUBITS);
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
-    const bool dbl = c->dtype == PW_C128;
     const uint64_t d = 1ull << c->n;
     SweepSums* sw = at<SweepSums>(c, c->L.sweep);
-    SweepSums* l2 = sw + SWEEP_SLOTS;
-    SweepSums* fin = l2 + SWEEP_L2;
-    FamilyRes* xr = at<FamilyRes>(c, c->L.xres);
-    int64_t nbatch = 0, nl2 = 0;
-    for (uint64_t x0 = 0; x0 < d; x0 += (uint64_t)c->batch) {
-        const int nb = (int)((d - x0) < (uint64_t)c->batch ? (d - x0) : (uint64_t)c->batch);
-        PW_HIP(eval_batch(c->P, dbl, c->psi, nullptr, x0, nb, eps, c->ws + c->L.work, at<FamilyRes>(c, c->L.parts),
-                          at<unsigned>(c, c->L.counters), xr, sw + nbatch, c->stream));
-        if (++nbatch == SWEEP_SLOTS) {
-            if (nl2 == SWEEP_L2) return fail(PW_ERR_UNSUPPORTED, "too many batches");
-            PW_HIP(reduce_sweep(sw, nbatch, l2 + nl2, c->stream));
-            ++nl2;
-            nbatch = 0;
-        }
+    SweepSums* fin = sw + SWEEP_SLOTS;
+    FamilyRes* fam = at<FamilyRes>(c, c->L.fam);
+    int64_t nchunk = 0;
+    for (uint64_t c0 = 0; c0 < d; c0 += (uint64_t)EXACT_CHUNK) {
+        const int64_t cnt = (int64_t)((d - c0) < (uint64_t)EXACT_CHUNK ? (d - c0) : (uint64_t)EXACT_CHUNK);
+        s = eval_device(c, nullptr, c0, cnt, eps, fam);
+        if (s != PW_OK) return s;
+        if (nchunk == SWEEP_SLOTS) return fail(PW_ERR_UNSUPPORTED, "too many chunks");
+        PW_HIP(reduce_families(fam, cnt, sw + nchunk, c->stream));
+        ++nchunk;
     }
-    if (nbatch > 0) {
-        PW_HIP(reduce_sweep(sw, nbatch, l2 + nl2, c->stream));
-        ++nl2;
-    }
-    PW_HIP(reduce_sweep(l2, nl2, fin, c->stream));
+    PW_HIP(reduce_sweep(sw, nchunk, fin, c->stream));
     SweepSums h;
     PW_HIP(hipMemcpyAsync(&h, fin, sizeof h, hipMemcpyDeviceToHost, c->stream));
     PW_HIP(hipStreamSynchronize(c->stream));
@@ -561,6 +619,63 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
     r.n_samples = drawn + 1;
     r.gap = gap;
     *out = r;
+    return PW_OK;
+}
+
+pw_status pw_set_moments(pw_ctx c, int max_alpha) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (max_alpha != 2 && max_alpha != 4) return fail(PW_ERR_ARG, "max_alpha must be 2 or 4, got %d", max_alpha);
+    c->max_alpha = max_alpha;
+    return PW_OK;
+}
+
+pw_status pw_timing_enable(pw_ctx c, int every) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (every < 0) return fail(PW_ERR_ARG, "every must be >= 0");
+    c->timing_every = every;
+    for (int k = 0; k < 4; ++k) {
+        c->launches[k] = 0;
+        c->active[k] = false;
+    }
+    return PW_OK;
+}
+
+pw_status pw_timing_read(pw_ctx c, int kclass, uint64_t* samples, double* total_ms, uint64_t* families) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (kclass < 0 || kclass > 3) return fail(PW_ERR_ARG, "kernel class %d outside [0, 3]", kclass);
+    for (auto& p : c->pending) {
+        PW_HIP(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        PW_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        c->total_ms[p.kclass] += ms;
+        c->samples[p.kclass] += 1;
+        c->sampled_families[p.kclass] += (uint64_t)p.families;
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+    if (samples) *samples = c->samples[kclass];
+    if (total_ms) *total_ms = c->total_ms[kclass];
+    if (families) *families = c->sampled_families[kclass];
+    return PW_OK;
+}
+
+pw_status pw_timing_reset(pw_ctx c) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    uint64_t a;
+    double b;
+    s = pw_timing_read(c, 0, &a, &b, &a);
+    if (s != PW_OK) return s;
+    for (int k = 0; k < 4; ++k) {
+        c->total_ms[k] = 0;
+        c->samples[k] = 0;
+        c->sampled_families[k] = 0;
+        c->launches[k] = 0;
+    }
     return PW_OK;
 }
 

@@ -52,13 +52,25 @@ struct Plan {
 
 Plan make_plan(int n, bool dbl);
 
+// Optional hook around kernel launches, used to time launches with HIP events
+// on the launch stream.  Kernel classes: 0 fused, 1 first pass, 2 middle column
+// pass, 3 final column pass.
+struct LaunchTimer {
+    void (*begin)(void* self, int kclass, hipStream_t st);
+    void (*end)(void* self, int kclass, int families, hipStream_t st);
+    void* self;
+};
+
 // Launchers (host side, enqueue on `st`).  All return hipSuccess or the first error.
 // Evaluate a batch of nb families.  If xs != nullptr the x of slot i is xs[i],
-// else it is x0 + i.  Per-family results go to out[i].  If batch_sum != nullptr
-// the fixed-order sum of the batch is also written there.
-hipError_t eval_batch(const Plan& P, bool dbl, const void* psi, const uint64_t* xs, uint64_t x0, int nb,
-                      double eps, void* work, FamilyRes* parts, unsigned* counters, FamilyRes* out,
-                      SweepSums* batch_sum, hipStream_t st);
+// else it is x0 + i.  Per-family results go to out[i].  max_alpha is 2 (moments
+// alpha = 2 only; m[1], m[2] are NaN) or 4.  parts holds nb * blocks_last partials.
+hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, const uint64_t* xs, uint64_t x0,
+                      int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
+                      const LaunchTimer* tm = nullptr);
+
+// Fixed-order sum of count per-family results.
+hipError_t reduce_families(const FamilyRes* in, int64_t count, SweepSums* out, hipStream_t st);
 
 // Transform only (no reductions): writes the 2^nh half-spectrum G of one x into work.
 hipError_t transform_one(const Plan& P, bool dbl, const void* psi, uint64_t x, void* work, hipStream_t st);

@@ -19,8 +19,8 @@
 // load time, coalesced) and column passes over the remaining bits (tiles of
 // 2^s rows by 2^w >= 128-byte columns, coalesced); the last column pass reduces
 // in registers and never writes the spectrum back.  Per-workgroup FP64 partials
-// are summed per family in a fixed order by the last workgroup to finish (an
-// atomic ticket), so results are bitwise reproducible.
+// are summed per family in a fixed order by a separate finalize kernel, so
+// results are bitwise reproducible.
 #include "common.h"
 #include <math.h>
 
@@ -136,6 +136,7 @@ __device__ __forceinline__ void load_products(const cx<R>* __restrict__ psi, int
 }
 
 // Per-thread accumulators in the transform precision, reduced in FP64.
+// gap holds the largest |F|^2 below (1 - eps)^2 (-1 if none).
 template <typename R>
 struct Acc {
     R s1, ent, s2, s3, s4, gap;
@@ -148,30 +149,44 @@ struct AccD {
     unsigned cnt;
 };
 
-// One magnitude |F| of the family: moments, Shannon term, nullity test.
-template <typename R>
-__device__ __forceinline__ void acc_mag(Acc<R>& A, R mag, R eps) {
-    const R a2 = mag * mag;
+template <typename R> struct Tiny;
+template <> struct Tiny<float> { static constexpr float v = 1e-30f; };
+template <> struct Tiny<double> { static constexpr double v = 1e-300; };
+
+// One squared magnitude a2 = |F|^2 of the family: moments up to alpha = MOM,
+// the Shannon term a2 log2 a2 (a2 below Tiny contributes below 1e-28), and the
+// nullity test ||F| - 1| < eps written as (1-eps)^2 < a2 < (1+eps)^2.
+template <typename R, int MOM>
+__device__ __forceinline__ void acc_sq(Acc<R>& A, R a2, R lo2, R hi2) {
     A.s1 += a2;
     const R a4 = a2 * a2;
     A.s2 += a4;
-    A.s3 = fma(a4, a2, A.s3);
-    A.s4 = fma(a4, a4, A.s4);
-    const R lg = a2 > R(0) ? Math<R>::lg2(a2) : R(0);
-    A.ent = fma(a2, lg, A.ent);
-    if (fabs(mag - R(1)) < eps) A.cnt += 1u;
-    else if (mag < R(1) - eps) A.gap = fmax(A.gap, mag);
+    if constexpr (MOM >= 3) A.s3 = fma(a4, a2, A.s3);
+    if constexpr (MOM >= 4) A.s4 = fma(a4, a4, A.s4);
+    A.ent = fma(a2, Math<R>::lg2(fmax(a2, Tiny<R>::v)), A.ent);
+    A.cnt += (a2 > lo2 && a2 < hi2) ? 1u : 0u;
+    A.gap = fmax(A.gap, a2 <= lo2 ? a2 : R(-1));
 }
 
-// Both magnitudes carried by one point G of the half-size spectrum.
-template <typename R>
-__device__ __forceinline__ void acc_point(Acc<R>& A, R gr, R gi, bool x0, R eps) {
+// Both magnitudes carried by each point G of the half-size spectrum:
+// x = 0: |Re G + Im G|, |Re G - Im G|;  x != 0: 2|Re G|, 2|Im G|.
+template <typename R, int RL, int MOM>
+__device__ __forceinline__ void acc_points(Acc<R>& A, const R (&re)[1 << RL], const R (&im)[1 << RL], bool x0, R lo2,
+                                           R hi2) {
     if (x0) {
-        acc_mag(A, fabs(gr + gi), eps);
-        acc_mag(A, fabs(gr - gi), eps);
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) {
+            const R u = re[j] + im[j], v = re[j] - im[j];
+            acc_sq<R, MOM>(A, u * u, lo2, hi2);
+            acc_sq<R, MOM>(A, v * v, lo2, hi2);
+        }
     } else {
-        acc_mag(A, R(2) * fabs(gr), eps);
-        acc_mag(A, R(2) * fabs(gi), eps);
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) {
+            const R u = re[j] + re[j], v = im[j] + im[j];
+            acc_sq<R, MOM>(A, u * u, lo2, hi2);
+            acc_sq<R, MOM>(A, v * v, lo2, hi2);
+        }
     }
 }
 
@@ -185,10 +200,9 @@ __device__ __forceinline__ void add_to(AccD& a, const AccD& b) {
     a.cnt += b.cnt;
 }
 
-// Fixed-order workgroup reduction; the total is valid in thread 0.
-template <int NT>
-__device__ AccD block_reduce(AccD a, AccD* sh) {
-    constexpr int WS = NT < 64 ? NT : 64;
+// Fixed-order reduction inside one wave (all lanes end with the same total).
+template <int WS>
+__device__ __forceinline__ AccD wave_reduce(AccD a) {
 #pragma unroll
     for (int off = WS / 2; off > 0; off >>= 1) {
         a.s1 += __shfl_xor(a.s1, off);
@@ -199,6 +213,13 @@ __device__ AccD block_reduce(AccD a, AccD* sh) {
         a.gap = fmax(a.gap, __shfl_xor(a.gap, off));
         a.cnt += __shfl_xor(a.cnt, off);
     }
+    return a;
+}
+
+// Fixed-order workgroup reduction; the total is valid in thread 0.
+template <int NT>
+__device__ AccD block_reduce(AccD a, AccD* sh) {
+    a = wave_reduce<(NT < 64 ? NT : 64)>(a);
     if constexpr (NT > 64) {
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         if (lane == 0) sh[wid] = a;
@@ -225,6 +246,7 @@ __device__ __forceinline__ AccD widen(const Acc<R>& a) {
     return d;
 }
 
+// Raw per-workgroup sums, stored in the FamilyRes layout.
 __device__ __forceinline__ FamilyRes raw_res(const AccD& a, uint64_t x) {
     FamilyRes r;
     r.x = x;
@@ -238,72 +260,38 @@ __device__ __forceinline__ FamilyRes raw_res(const AccD& a, uint64_t x) {
     return r;
 }
 
-// Scale raw sums by the exact powers of two d^-alpha (d = 2^n).
-__device__ __forceinline__ FamilyRes scaled(FamilyRes r, int n) {
-    r.p = ldexp(r.p, -n);
-    r.m[0] = ldexp(r.m[0], -2 * n);
-    r.m[1] = ldexp(r.m[1], -3 * n);
-    r.m[2] = ldexp(r.m[2], -4 * n);
+__device__ __forceinline__ AccD acc_of(const FamilyRes& r) {
+    AccD a;
+    a.s1 = r.p;
+    a.ent = r.ent;
+    a.s2 = r.m[0];
+    a.s3 = r.m[1];
+    a.s4 = r.m[2];
+    a.gap = r.gap;
+    a.cnt = (unsigned)r.nu;
+    return a;
+}
+
+// Final per-family values: exact power-of-two scaling by d^-alpha (d = 2^n) and
+// the gap as a magnitude.  Moments above MOM are reported as NaN (not computed).
+template <int MOM>
+__device__ __forceinline__ FamilyRes finish(const AccD& a, uint64_t x, int n) {
+    FamilyRes r;
+    r.x = x;
+    r.p = ldexp(a.s1, -n);
+    r.ent = a.ent;
+    r.m[0] = ldexp(a.s2, -2 * n);
+    r.m[1] = MOM >= 3 ? ldexp(a.s3, -3 * n) : __builtin_nan("");
+    r.m[2] = MOM >= 4 ? ldexp(a.s4, -4 * n) : __builtin_nan("");
+    r.gap = a.gap >= 0.0 ? sqrt(a.gap) : -1.0;
+    r.nu = a.cnt;
     return r;
 }
 
-__device__ __forceinline__ void add_res(FamilyRes& a, const FamilyRes& b) {
-    a.p += b.p;
-    a.ent += b.ent;
-    a.m[0] += b.m[0];
-    a.m[1] += b.m[1];
-    a.m[2] += b.m[2];
-    a.gap = fmax(a.gap, b.gap);
-    a.nu += b.nu;
-}
-
-// Fixed-order sum of v[0..count) by the NT threads of one workgroup: thread t
-// adds v[t], v[t + NT], ... in order, then a fixed pairwise tree.  Valid in thread 0.
-template <int NT>
-__device__ FamilyRes block_sum_res(const FamilyRes* v, int64_t count, FamilyRes* sh) {
-    FamilyRes t;
-    t.x = 0;
-    t.p = t.ent = t.m[0] = t.m[1] = t.m[2] = 0.0;
-    t.gap = -1.0;
-    t.nu = 0;
-    for (int64_t i = threadIdx.x; i < count; i += NT) add_res(t, v[i]);
-    sh[threadIdx.x] = t;
-    __syncthreads();
-#pragma unroll
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) add_res(sh[threadIdx.x], sh[threadIdx.x + h]);
-        __syncthreads();
-    }
-    return sh[0];
-}
-
-// The last of the nb family finalisers sums the batch into *batch_sum.
-template <int NT>
-__device__ void batch_ticket(FamilyRes* out, int nb, unsigned* ticket, SweepSums* batch_sum, FamilyRes* sh,
-                             unsigned* s_flag) {
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(ticket, 1u);
-        *s_flag = (prev == (unsigned)nb - 1u) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (*s_flag) {
-        __threadfence();
-        const FamilyRes t = block_sum_res<NT>(out, nb, sh);
-        if (threadIdx.x == 0) {
-            SweepSums s;
-            s.S[0] = t.m[0];
-            s.S[1] = t.m[1];
-            s.S[2] = t.m[2];
-            s.L = t.ent;
-            s.P = t.p;
-            s.gap = t.gap;
-            s.nu_cnt = t.nu;
-            s.count = (uint64_t)nb;
-            *batch_sum = s;
-            atomicExch(ticket, 0u);
-        }
-    }
+template <typename R>
+__device__ __forceinline__ void thresholds(R eps, R& lo2, R& hi2) {
+    lo2 = (R(1) - eps) * (R(1) - eps);
+    hi2 = (R(1) + eps) * (R(1) + eps);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,29 +299,26 @@ __device__ void batch_ticket(FamilyRes* out, int nb, unsigned* ticket, SweepSums
 // ---------------------------------------------------------------------------
 
 // Whole family in one workgroup (n - 1 = K).  Grid: one block per family.
-template <typename R, int TL, int RL>
+template <typename R, int TL, int RL, int MOM>
 __global__ void __launch_bounds__(1 << TL)
 k_fused(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
-        FamilyRes* __restrict__ out, unsigned* __restrict__ counters, SweepSums* __restrict__ batch_sum, int nb) {
+        FamilyRes* __restrict__ out) {
     constexpr int K = TL + RL;
     constexpr int NT = 1 << TL;
-    constexpr int RED = NT < 64 ? 64 : NT;
     __shared__ cx<R> lds[Lds<K>::elems];
-    __shared__ AccD shw[RED / 64];
-    __shared__ FamilyRes shr[NT];
-    __shared__ unsigned s_flag;
+    __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
     const uint32_t slot = blockIdx.x;
     const uint64_t x = xs ? xs[slot] : x0 + slot;
     R re[1 << RL], im[1 << RL];
     load_products<R, TL, RL>(psi, n - 1, (uint32_t)x, 0u, re, im);
     tile_fwht<R, TL, RL>(re, im, lds, 0);
+    R lo2, hi2;
+    thresholds(eps, lo2, hi2);
     Acc<R> acc;
     acc.init();
-#pragma unroll
-    for (int j = 0; j < (1 << RL); ++j) acc_point(acc, re[j], im[j], x == 0, eps);
+    acc_points<R, RL, MOM>(acc, re, im, x == 0, lo2, hi2);
     const AccD tot = block_reduce<NT>(widen(acc), shw);
-    if (threadIdx.x == 0) out[slot] = scaled(raw_res(tot, x), n);
-    if (batch_sum) batch_ticket<NT>(out, nb, &counters[0], batch_sum, shr, &s_flag);
+    if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, n);
 }
 
 // First pass of a multi-pass transform: products + low K index bits of one tile.
@@ -362,12 +347,12 @@ k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
 
 // Column pass over index bits [lo, lo + s) of every family in the batch.
 // A tile is 2^s rows (stride 2^lo) by 2^w consecutive columns, w = K - s.
-// Grid: (2^(nh - K), families).  LAST: reduce instead of writing back.
-template <typename R, int TL, int RL, bool LAST>
+// Grid: (2^(nh - K), families).  LAST: reduce to one partial per workgroup
+// (parts[family][block]) instead of writing the spectrum back.
+template <typename R, int TL, int RL, bool LAST, int MOM>
 __global__ void __launch_bounds__(1 << TL)
 k_column(cx<R>* __restrict__ work, int n, int lo, int s, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
-         FamilyRes* __restrict__ parts, unsigned* __restrict__ counters, FamilyRes* __restrict__ out,
-         SweepSums* __restrict__ batch_sum, int nb) {
+         FamilyRes* __restrict__ parts) {
     constexpr int K = TL + RL;
     constexpr int NT = 1 << TL;
     __shared__ cx<R> lds[Lds<K>::elems];
@@ -399,34 +384,70 @@ k_column(cx<R>* __restrict__ work, int n, int lo, int s, const uint64_t* __restr
         }
     } else {
         __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
-        __shared__ FamilyRes shr[NT];
-        __shared__ unsigned s_flag;
         const uint64_t x = xs ? xs[slot] : x0 + slot;
+        R lo2, hi2;
+        thresholds(eps, lo2, hi2);
         Acc<R> acc;
         acc.init();
-#pragma unroll
-        for (int j = 0; j < (1 << RL); ++j) acc_point(acc, re[j], im[j], x == 0, eps);
+        acc_points<R, RL, MOM>(acc, re, im, x == 0, lo2, hi2);
         const AccD tot = block_reduce<NT>(widen(acc), shw);
-        const int nblk = (int)gridDim.x;
-        if (threadIdx.x == 0) {
-            parts[(size_t)slot * nblk + bid] = raw_res(tot, x);
-            __threadfence();
-            const unsigned prev = atomicAdd(&counters[slot], 1u);
-            s_flag = (prev == (unsigned)nblk - 1u) ? 1u : 0u;
+        if (threadIdx.x == 0) parts[(size_t)slot * gridDim.x + bid] = raw_res(tot, x);
+    }
+}
+
+// Per-family fixed-order sum of the final pass's partials.  Grid: one wave per family.
+template <int MOM>
+__global__ void __launch_bounds__(64)
+k_finalize(const FamilyRes* __restrict__ parts, int nblk, int n, FamilyRes* __restrict__ out) {
+    const FamilyRes* p = parts + (size_t)blockIdx.x * nblk;
+    AccD a;
+    a.s1 = a.ent = a.s2 = a.s3 = a.s4 = 0.0;
+    a.gap = -1.0;
+    a.cnt = 0u;
+    for (int i = threadIdx.x; i < nblk; i += 64) add_to(a, acc_of(p[i]));
+    a = wave_reduce<64>(a);
+    if (threadIdx.x == 0) out[blockIdx.x] = finish<MOM>(a, p[0].x, n);
+}
+
+// Fixed-order sum of count per-family results into one SweepSums.
+__global__ void __launch_bounds__(256)
+k_reduce_fam(const FamilyRes* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
+    constexpr int NT = 256;
+    __shared__ SweepSums sh[NT];
+    SweepSums t;
+    t.S[0] = t.S[1] = t.S[2] = t.L = t.P = 0.0;
+    t.gap = -1.0;
+    t.nu_cnt = 0;
+    t.count = 0;
+    for (int64_t i = threadIdx.x; i < count; i += NT) {
+        const FamilyRes v = in[i];
+        t.S[0] += v.m[0];
+        t.S[1] += v.m[1];
+        t.S[2] += v.m[2];
+        t.L += v.ent;
+        t.P += v.p;
+        t.gap = fmax(t.gap, v.gap);
+        t.nu_cnt += v.nu;
+        t.count += 1;
+    }
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            SweepSums& a = sh[threadIdx.x];
+            const SweepSums& b = sh[threadIdx.x + h];
+            a.S[0] += b.S[0];
+            a.S[1] += b.S[1];
+            a.S[2] += b.S[2];
+            a.L += b.L;
+            a.P += b.P;
+            a.gap = fmax(a.gap, b.gap);
+            a.nu_cnt += b.nu_cnt;
+            a.count += b.count;
         }
         __syncthreads();
-        if (s_flag) {
-            __threadfence();
-            FamilyRes t = block_sum_res<NT>(parts + (size_t)slot * nblk, nblk, shr);
-            if (threadIdx.x == 0) {
-                t.x = x;
-                out[slot] = scaled(t, n);
-                atomicExch(&counters[slot], 0u);
-            }
-            __syncthreads();
-            if (batch_sum) batch_ticket<NT>(out, nb, &counters[nb], batch_sum, shr, &s_flag);
-        }
     }
+    if (threadIdx.x == 0) *out = sh[0];
 }
 
 // c(x, z) = (-i)^{|x&z|} F_x(z) from the half spectrum G of one family.
@@ -452,7 +473,8 @@ __global__ void k_signed(const cx<R>* __restrict__ G, int n, uint32_t x, double*
     c[z] = v;
 }
 
-__global__ void k_reduce_sweep(const SweepSums* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
+__global__ void __launch_bounds__(256)
+k_reduce_sweep(const SweepSums* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
     constexpr int NT = 256;
     __shared__ SweepSums sh[NT];
     SweepSums t;
@@ -497,81 +519,85 @@ constexpr int K_FIRST = 12;
 template <typename R> struct ColShape;
 template <> struct ColShape<float> { static constexpr int TL = 9, RL = 4; };
 template <> struct ColShape<double> { static constexpr int TL = 8, RL = 4; };
-template <typename R> constexpr int fused_max() { return sizeof(R) == 4 ? 13 : 12; }
 
-template <typename R, int K>
+template <typename R, int K, int MOM>
 hipError_t launch_fused_k(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
-                          unsigned* counters, SweepSums* bs, hipStream_t st) {
-    constexpr int RL = K < 4 ? K : 4;
-    constexpr int TL = K == 13 ? 9 : K - RL;
-    constexpr int RLx = K - TL;
-    hipLaunchKernelGGL((k_fused<R, TL, RLx>), dim3(nb), dim3(1 << TL), 0, st, (const cx<R>*)psi, n, xs, x0, eps, out,
-                       counters, bs, nb);
+                          hipStream_t st) {
+    constexpr int RL0 = K < 4 ? K : 4;
+    constexpr int TL = K == 13 ? 9 : K - RL0;
+    constexpr int RL = K - TL;
+    hipLaunchKernelGGL((k_fused<R, TL, RL, MOM>), dim3(nb), dim3(1 << TL), 0, st, (const cx<R>*)psi, n, xs, x0, eps,
+                       out);
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename R, int MOM>
 hipError_t launch_fused(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
-                        unsigned* counters, SweepSums* bs, hipStream_t st) {
+                        hipStream_t st) {
     switch (n - 1) {
 #define PW_CASE(K) \
-    case K: return launch_fused_k<R, K>(psi, n, xs, x0, nb, eps, out, counters, bs, st);
+    case K: return launch_fused_k<R, K, MOM>(psi, n, xs, x0, nb, eps, out, st);
         PW_CASE(0) PW_CASE(1) PW_CASE(2) PW_CASE(3) PW_CASE(4) PW_CASE(5) PW_CASE(6)
         PW_CASE(7) PW_CASE(8) PW_CASE(9) PW_CASE(10) PW_CASE(11) PW_CASE(12)
 #undef PW_CASE
         case 13:
-            if constexpr (sizeof(R) == 4) return launch_fused_k<R, 13>(psi, n, xs, x0, nb, eps, out, counters, bs, st);
+            if constexpr (sizeof(R) == 4) return launch_fused_k<R, 13, MOM>(psi, n, xs, x0, nb, eps, out, st);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename R>
+template <typename R, int MOM>
 hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, double eps,
-                        void* work, FamilyRes* parts, unsigned* counters, FamilyRes* out, SweepSums* bs,
-                        hipStream_t st) {
+                        void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st, const LaunchTimer* tm) {
     if (nb <= 0) return hipSuccess;
     const R e = (R)eps;
-    if (P.fused) return launch_fused<R>(psi, P.n, xs, x0, nb, e, out, counters, bs, st);
+    if (P.fused) {
+        if (tm) tm->begin(tm->self, 0, st);
+        hipError_t err = launch_fused<R, MOM>(psi, P.n, xs, x0, nb, e, out, st);
+        if (tm) tm->end(tm->self, 0, nb, st);
+        return err;
+    }
     constexpr int TL = ColShape<R>::TL, RL = ColShape<R>::RL;
+    if (tm) tm->begin(tm->self, 1, st);
     hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (P.nh - K_FIRST), nb), dim3(256), 0, st, (const cx<R>*)psi,
                        P.n, xs, x0, (cx<R>*)work);
+    if (tm) tm->end(tm->self, 1, nb, st);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const dim3 grid(1u << (P.nh - (TL + RL)), nb);
     for (int i = 0; i < P.npass; ++i) {
-        if (i + 1 < P.npass) {
-            hipLaunchKernelGGL((k_column<R, TL, RL, false>), grid, dim3(1 << TL), 0, st, (cx<R>*)work, P.n, P.lo[i],
-                               P.s[i], xs, x0, e, parts, counters, out, bs, nb);
+        const bool last = i + 1 == P.npass;
+        if (tm) tm->begin(tm->self, last ? 3 : 2, st);
+        if (!last) {
+            hipLaunchKernelGGL((k_column<R, TL, RL, false, MOM>), grid, dim3(1 << TL), 0, st, (cx<R>*)work, P.n,
+                               P.lo[i], P.s[i], xs, x0, e, parts);
         } else {
-            hipLaunchKernelGGL((k_column<R, TL, RL, true>), grid, dim3(1 << TL), 0, st, (cx<R>*)work, P.n, P.lo[i],
-                               P.s[i], xs, x0, e, parts, counters, out, bs, nb);
+            hipLaunchKernelGGL((k_column<R, TL, RL, true, MOM>), grid, dim3(1 << TL), 0, st, (cx<R>*)work, P.n,
+                               P.lo[i], P.s[i], xs, x0, e, parts);
         }
+        if (tm) tm->end(tm->self, last ? 3 : 2, nb, st);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    return hipSuccess;
+    hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, (int)grid.x, P.n, out);
+    return hipGetLastError();
 }
 
 template <typename R>
 hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* work, hipStream_t st) {
-    // multi-pass schedule without the final reduction; also used for fused sizes
-    // (a first pass over min(nh, 12) bits and column passes for the rest)
+    // the multi-pass schedule without the final reduction
     constexpr int TL = ColShape<R>::TL, RL = ColShape<R>::RL;
     const int nh = P.nh;
-    if (nh <= K_FIRST) {
-        // tiny: use the column kernel machinery is not possible; fall back to the
-        // first-pass kernel with a tile equal to the whole half spectrum
-        return hipErrorInvalidValue;
-    }
+    if (P.fused || nh <= K_FIRST) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (nh - K_FIRST), 1), dim3(256), 0, st, (const cx<R>*)psi, P.n,
                        (const uint64_t*)nullptr, x, (cx<R>*)work);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
-        hipLaunchKernelGGL((k_column<R, TL, RL, false>), dim3(1u << (nh - (TL + RL)), 1), dim3(1 << TL), 0, st,
+        hipLaunchKernelGGL((k_column<R, TL, RL, false, 2>), dim3(1u << (nh - (TL + RL)), 1), dim3(1 << TL), 0, st,
                            (cx<R>*)work, P.n, P.lo[i], P.s[i], (const uint64_t*)nullptr, x, (R)0,
-                           (FamilyRes*)nullptr, (unsigned*)nullptr, (FamilyRes*)nullptr, (SweepSums*)nullptr, 1);
+                           (FamilyRes*)nullptr);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -611,11 +637,19 @@ Plan make_plan(int n, bool dbl) {
     return P;
 }
 
-hipError_t eval_batch(const Plan& P, bool dbl, const void* psi, const uint64_t* xs, uint64_t x0, int nb, double eps,
-                      void* work, FamilyRes* parts, unsigned* counters, FamilyRes* out, SweepSums* batch_sum,
-                      hipStream_t st) {
-    return dbl ? eval_batch_t<double>(P, psi, xs, x0, nb, eps, work, parts, counters, out, batch_sum, st)
-               : eval_batch_t<float>(P, psi, xs, x0, nb, eps, work, parts, counters, out, batch_sum, st);
+hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, const uint64_t* xs, uint64_t x0,
+                      int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
+                      const LaunchTimer* tm) {
+    if (dbl)
+        return max_alpha >= 4 ? eval_batch_t<double, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm)
+                              : eval_batch_t<double, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm);
+    return max_alpha >= 4 ? eval_batch_t<float, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm)
+                          : eval_batch_t<float, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm);
+}
+
+hipError_t reduce_families(const FamilyRes* in, int64_t count, SweepSums* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_fam, dim3(1), dim3(256), 0, st, in, count, out);
+    return hipGetLastError();
 }
 
 hipError_t transform_one(const Plan& P, bool dbl, const void* psi, uint64_t x, void* work, hipStream_t st) {

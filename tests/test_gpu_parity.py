@@ -253,3 +253,34 @@ def test_errors_reported():
         ctx.upload(bad, pw.PW_C128)
     assert e.value.status == 3
     ctx.close()
+
+
+def test_moments_alpha2_only_matches_full():
+    n = 15
+    psi = synth.haar_state(n, 901)
+    xs = _sample_xs(n, 6, 902)
+    ctx = make_ctx(psi, pw.PW_C128)
+    log("moments alpha=2 only n=%d" % n)
+    full = ctx.eval_x(xs, 1e-7)
+    ex_full = ctx.exact(1e-7)
+    pw.pw_set_moments(ctx.h, 2)
+    part = ctx.eval_x(xs, 1e-7)
+    ex_part = ctx.exact(1e-7)
+    ctx.close()
+    assert np.array_equal(full["m"][:, 0], part["m"][:, 0])
+    assert np.array_equal(full["ent"], part["ent"]) and np.array_equal(full["nu"], part["nu"])
+    assert np.all(np.isnan(part["m"][:, 1:]))
+    assert ex_full["S"][0] == ex_part["S"][0] and math.isnan(ex_part["M"][1])
+
+
+def test_exact_is_bitwise_reproducible():
+    n = 17
+    psi = synth.haar_state(n, 903).astype(np.complex64)
+    ctx = make_ctx(psi, pw.PW_C64)
+    log("reproducibility n=%d" % n)
+    a = ctx.exact(1e-4)
+    b = ctx.exact(1e-4)
+    ctx.close()
+    # bitwise: every double and count identical (NaN entries compare as text)
+    import json
+    assert json.dumps(a, sort_keys=True) == json.dumps(b, sort_keys=True)
