@@ -28,7 +28,25 @@ N_QUBITS = 20
 ETA = 20
 N_T = 20
 HBM_PEAK_GBS = 8000.0
+# FP32 VALU issue peak with packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 KCLASS = {0: "k_fused", 1: "k_first", 2: "k_column(mid)", 3: "k_column(last)"}
+# kernel-name prefixes as rocprofv3 reports them (first pass: shared-tile variant for sweeps)
+KNAME = {0: "k_fused", 1: "k_first_shared", 2: "k_column", 3: "k_column"}
+
+
+def algorithmic_ops_per_point(kclass, n, bits_in_pass):
+    """Minimal VALU operations per point of the half-size spectrum for one kernel class:
+    product conj(a) c = 4 (2 mul + 2 fma); each radix-2 stage 2 (re and im add/sub);
+    reductions per magnitude 7 (square, sum, fourth power, sum, log2, Shannon fma,
+    running max for the nullity test), two magnitudes per point."""
+    if kclass == 0:
+        return 4 + 2 * (n - 1) + 14
+    if kclass == 1:
+        return 4 + 2 * 12
+    if kclass == 2:
+        return 2 * bits_in_pass
+    return 2 * bits_in_pass + 14
 
 
 def kernel_source_hash():
@@ -158,18 +176,30 @@ def main():
     strings = float(1 << n) ** 2
     value = args.steps * strings / el64
 
-    # dominant kernel = largest share of the sampled time per family
+    # dominant kernel = largest share of the sampled time per family.  At N = 20 the state
+    # (8 MiB) and the batch's half spectra (256 MiB) stay in L2/MALL, so the roof that binds
+    # is VALU issue, not HBM: achieved = algorithmic VALU operations per launch / duration.
     dom = max(kt64, key=lambda k: kt64[k]["avg_ms"] / kt64[k]["families_per_launch"])
     d = kt64[dom]
-    alg_bytes = d["families_per_launch"] * float(1 << n) * 8.0       # one read of psi per family (complex64)
-    achieved = alg_bytes / (d["avg_ms"] * 1e-3) / 1e9
-    traffic = load_traffic(KCLASS[dom], "c64")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
+    half_points = float(1 << (n - 1))
+    ops_pt = algorithmic_ops_per_point(dom, n, (n - 1) - 12)
+    alg_ops = d["families_per_launch"] * half_points * ops_pt
+    achieved = alg_ops / (d["avg_ms"] * 1e-3) / 1e9
+    path_us = sum(v["avg_ms"] * 1e3 / v["families_per_launch"] for v in kt64.values())
+    alg_bytes_family = float(1 << n) * 8.0       # one read of psi per family (complex64)
+    traffic = load_traffic(KNAME[dom], "c64")
+    roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
+                "frac": round(achieved / VALU_PEAK_GOPS, 4),
                 "traffic": traffic, "kernel": KCLASS[dom],
                 "kernel_avg_us": round(d["avg_ms"] * 1e3, 2), "families_per_launch": d["families_per_launch"],
-                "algorithmic_bytes_per_launch": alg_bytes,
-                "per_class_avg_us": {KCLASS[k]: round(v["avg_ms"] * 1e3, 2) for k, v in kt64.items()}}
+                "algorithmic_ops_per_point": ops_pt,
+                "algorithmic_ops_per_launch": alg_ops,
+                "per_class_avg_us": {KCLASS[k]: round(v["avg_ms"] * 1e3, 2) for k, v in kt64.items()},
+                "path_us_per_family": round(path_us, 4),
+                "hbm_equivalent": {"algorithmic_bytes_per_family": alg_bytes_family,
+                                   "GBps": round(alg_bytes_family / (path_us * 1e-6) / 1e9, 1),
+                                   "note": "one read of psi per family over the whole path time; psi and the "
+                                           "intermediates are served from L2/MALL at this size"}}
 
     el128 = r128 = None
     if args.steps_c128 > 0:

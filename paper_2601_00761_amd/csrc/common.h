@@ -45,6 +45,7 @@ struct Plan {
     bool fused;     // whole transform inside one workgroup (nh <= small limit)
     int k1;         // bits of the first pass
     int npass;      // number of column passes after the first
+    int ktile;      // index bits per column-pass tile (12, or 13 when that saves a pass)
     int lo[4];
     int s[4];
     int blocks_last;   // workgroups per family in the final pass

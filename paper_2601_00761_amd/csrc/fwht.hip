@@ -13,14 +13,15 @@
 // each of the 2^TL threads keeps 2^RL points in registers, radix-2 stages over
 // the register bits run in registers, and an LDS exchange (padded one element in
 // sixteen against bank conflicts) re-maps another block of RL index bits into
-// registers.  Small states (n - 1 <= 13 single / 12 double) run the whole
-// transform and the reductions in one workgroup per family.  Larger states use a
-// first pass over the low 12 index bits (contiguous tiles, products formed at
-// load time, coalesced) and column passes over the remaining bits (tiles of
-// 2^s rows by 2^w >= 128-byte columns, coalesced); the last column pass reduces
-// in registers and never writes the spectrum back.  Per-workgroup FP64 partials
-// are summed per family in a fixed order by a separate finalize kernel, so
-// results are bitwise reproducible.
+// registers.  The sequence of register windows is fixed at compile time, so
+// every LDS and global address is a per-thread base plus an immediate offset.
+// Small states (n - 1 <= 13 single / 12 double) run the whole transform and the
+// reductions in one workgroup per family.  Larger states use a first pass over
+// the low 12 index bits (contiguous tiles, products formed at load time) and
+// column passes over the remaining bits (tiles of 2^s rows by 2^w >= 128-byte
+// columns); the last column pass reduces in registers and never writes the
+// spectrum back.  Per-workgroup FP64 partials are summed per family in a fixed
+// order by a separate finalize kernel, so results are bitwise reproducible.
 #include "common.h"
 #include <math.h>
 
@@ -30,81 +31,102 @@ namespace {
 template <typename R> struct Math;
 template <> struct Math<float> {
     static __device__ __forceinline__ float lg2(float v) { return __log2f(v); }
+    static constexpr float tiny = 1e-30f;
 };
 template <> struct Math<double> {
     static __device__ __forceinline__ double lg2(double v) { return log2(v); }
+    static constexpr double tiny = 1e-300;
 };
 
-__device__ __forceinline__ uint32_t win_idx(uint32_t tid, uint32_t j, int a, int rl) {
-    return (tid & ((1u << a) - 1u)) | (j << a) | ((tid >> a) << (a + rl));
+// Window layout: register bits [A, A + RL) of the tile index, thread bits the rest.
+template <int A, int RL>
+__device__ __forceinline__ uint32_t thread_part(uint32_t tid) {
+    return (tid & ((1u << A) - 1u)) | ((tid >> A) << (A + RL));
 }
+__host__ __device__ constexpr uint32_t padc(uint32_t i) { return i + (i >> 4); }
 __device__ __forceinline__ uint32_t padi(uint32_t i) { return i + (i >> 4); }
 
 template <int K> struct Lds { static constexpr int elems = (1 << K) + ((1 << K) >> 4); };
 
-// Radix-2 butterflies (u, v) -> (u + v, u - v) over register bits [b0, b1).
-template <typename R, int RL>
-__device__ __forceinline__ void reg_stages(R (&re)[1 << RL], R (&im)[1 << RL], int b0, int b1) {
+// Radix-2 butterflies (u, v) -> (u + v, u - v) over register bits [B0, B1).
+template <typename R, int RL, int B0, int B1>
+__device__ __forceinline__ void reg_stages(R (&re)[1 << RL], R (&im)[1 << RL]) {
 #pragma unroll
-    for (int b = 0; b < RL; ++b) {
-        if (b >= b0 && b < b1) {
+    for (int b = B0; b < B1; ++b) {
 #pragma unroll
-            for (int j = 0; j < (1 << RL); ++j) {
-                if (!(j & (1 << b))) {
-                    const int k = j | (1 << b);
-                    const R ar = re[j], ai = im[j], br = re[k], bi = im[k];
-                    re[j] = ar + br;
-                    im[j] = ai + bi;
-                    re[k] = ar - br;
-                    im[k] = ai - bi;
-                }
+        for (int j = 0; j < (1 << RL); ++j) {
+            if (!(j & (1 << b))) {
+                const int k = j | (1 << b);
+                const R ar = re[j], ai = im[j], br = re[k], bi = im[k];
+                re[j] = ar + br;
+                im[j] = ai + bi;
+                re[k] = ar - br;
+                im[k] = ai - bi;
             }
         }
     }
 }
 
-// Move the points from window layout a_old to window layout a_new through LDS.
-template <typename R, int TL, int RL>
-__device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds, int a_old, int a_new) {
+// Move the points from window AO to window AN through LDS.  The address of
+// (thread t, register j) in window A is pad(T_A(t) | j 2^A) = pad(T_A(t)) + pad(j 2^A)
+// (the two parts have disjoint bits), i.e. a per-thread base plus a constant.
+template <typename R, int TL, int RL, int AO, int AN>
+__device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds) {
     const uint32_t tid = threadIdx.x;
+    cx<R>* wo = lds + padi(thread_part<AO, RL>(tid));
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) {
         cx<R> v;
         v.re = re[j];
         v.im = im[j];
-        lds[padi(win_idx(tid, j, a_old, RL))] = v;
+        wo[padc((uint32_t)j << AO)] = v;
     }
     __syncthreads();
+    const cx<R>* rn = lds + padi(thread_part<AN, RL>(tid));
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) {
-        const cx<R> v = lds[padi(win_idx(tid, j, a_new, RL))];
+        const cx<R> v = rn[padc((uint32_t)j << AN)];
         re[j] = v.re;
         im[j] = v.im;
     }
     __syncthreads();
 }
 
-// Unnormalised WHT over bits [lo_bit, K) of the tile index.  On entry thread t
-// holds points t + j 2^TL (window a = TL); returns the window of the result.
-template <typename R, int TL, int RL>
-__device__ __forceinline__ int tile_fwht(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds, int lo_bit) {
-    constexpr int K = TL + RL;
-    int a = TL, hi = K;
-    int lo = max(a, lo_bit);
-    if (lo < hi) reg_stages<R, RL>(re, im, lo - a, hi - a);
-    hi = lo;
-    while (hi > lo_bit) {
-        const int na = max(hi - RL, 0);
-        exchange<R, TL, RL>(re, im, lds, a, na);
-        a = na;
-        lo = max(a, lo_bit);
-        reg_stages<R, RL>(re, im, lo - a, hi - a);
-        hi = lo;
-    }
-    return a;
+// After the first round (window TL, register bits [max(TL, LO), K)), the bits
+// [LO, TL) are taken in blocks of RL from the bottom: window B0 transforms
+// [B0, min(B0 + RL, TL)).  The result stays in the last window, whose low
+// threads hold consecutive indices (coalesced stores).
+template <int TL, int RL, int LO>
+constexpr int final_window() {
+    if (LO >= TL) return TL;
+    int b0 = LO;
+    while (b0 + RL < TL) b0 += RL;
+    return b0;
 }
 
-// f values of the half-size problem at half indices (tile << K) + t + j 2^TL.
+template <typename R, int TL, int RL, int A, int B0>
+struct Rounds {
+    static __device__ __forceinline__ void run(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds) {
+        if constexpr (B0 < TL) {
+            exchange<R, TL, RL, A, B0>(re, im, lds);
+            constexpr int B1 = (B0 + RL < TL) ? B0 + RL : TL;
+            reg_stages<R, RL, 0, B1 - B0>(re, im);
+            Rounds<R, TL, RL, B0, B0 + RL>::run(re, im, lds);
+        }
+    }
+};
+
+// Unnormalised WHT over bits [LO, K) of the tile index.  On entry thread t holds
+// points t + j 2^TL (window TL); on exit the points are in final_window().
+template <typename R, int TL, int RL, int LO>
+__device__ __forceinline__ void tile_fwht(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds) {
+    constexpr int S0 = LO > TL ? LO : TL;
+    reg_stages<R, RL, S0 - TL, RL>(re, im);
+    Rounds<R, TL, RL, TL, LO>::run(re, im, lds);
+}
+
+// f values of the half-size problem at half indices (tile << K) + t + j 2^TL
+// (general x; used by the single-workgroup kernel and for x < 2^K).
 template <typename R, int TL, int RL>
 __device__ __forceinline__ void load_products(const cx<R>* __restrict__ psi, int nh, uint32_t x, uint32_t tile,
                                               R (&re)[1 << RL], R (&im)[1 << RL]) {
@@ -124,70 +146,115 @@ __device__ __forceinline__ void load_products(const cx<R>* __restrict__ psi, int
         }
     } else {
         const uint32_t half = 1u << nh;
+        const cx<R>* pa = psi + (tile << K) + tid;
+        const cx<R>* pc = pa + half;
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
-            const uint32_t bp = (tile << K) + tid + ((uint32_t)j << TL);
-            const cx<R> a = psi[bp];
-            const cx<R> c = psi[bp + half];
+            const cx<R> a = pa[(uint32_t)j << TL];
+            const cx<R> c = pc[(uint32_t)j << TL];
             re[j] = a.re * a.re + a.im * a.im;
             im[j] = c.re * c.re + c.im * c.im;
         }
     }
 }
 
-// Per-thread accumulators in the transform precision, reduced in FP64.
-// gap holds the largest |F|^2 below (1 - eps)^2 (-1 if none).
-template <typename R>
-struct Acc {
-    R s1, ent, s2, s3, s4, gap;
-    unsigned cnt;
-    __device__ void init() { s1 = ent = s2 = s3 = s4 = R(0); gap = R(-1); cnt = 0u; }
-};
+// Same for x >= 2^K: the top bit p >= K only moves the tile, so the state
+// tile is tu << K and the partner tile (tu ^ (x >> K)) << K, read at l ^ (x mod 2^K).
+template <typename R, int TL, int RL>
+__device__ __forceinline__ void load_products_hi(const cx<R>* __restrict__ psi, uint32_t x, uint32_t tile,
+                                                 R (&re)[1 << RL], R (&im)[1 << RL]) {
+    constexpr int K = TL + RL;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t xh = x >> K, xl = x & ((1u << K) - 1u);
+    const int q = 31 - __builtin_clz(xh);
+    const uint32_t lowm = (1u << q) - 1u;
+    const uint32_t tu = (tile & lowm) | ((tile & ~lowm) << 1);
+    const cx<R>* pa = psi + ((size_t)tu << K) + tid;
+    const cx<R>* pc = psi + ((size_t)(tu ^ xh) << K) + (tid ^ (xl & ((1u << TL) - 1u)));
+    const uint32_t jx = xl >> TL;
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) {
+        const cx<R> a = pa[(uint32_t)j << TL];
+        const cx<R> c = pc[((uint32_t)j ^ jx) << TL];
+        re[j] = a.re * c.re + a.im * c.im;
+        im[j] = a.re * c.im - a.im * c.re;
+    }
+}
 
 struct AccD {
     double s1, ent, s2, s3, s4, gap;
     unsigned cnt;
 };
 
-template <typename R> struct Tiny;
-template <> struct Tiny<float> { static constexpr float v = 1e-30f; };
-template <> struct Tiny<double> { static constexpr double v = 1e-300; };
-
-// One squared magnitude a2 = |F|^2 of the family: moments up to alpha = MOM,
-// the Shannon term a2 log2 a2 (a2 below Tiny contributes below 1e-28), and the
-// nullity test ||F| - 1| < eps written as (1-eps)^2 < a2 < (1+eps)^2.
-template <typename R, int MOM>
-__device__ __forceinline__ void acc_sq(Acc<R>& A, R a2, R lo2, R hi2) {
-    A.s1 += a2;
-    const R a4 = a2 * a2;
-    A.s2 += a4;
-    if constexpr (MOM >= 3) A.s3 = fma(a4, a2, A.s3);
-    if constexpr (MOM >= 4) A.s4 = fma(a4, a4, A.s4);
-    A.ent = fma(a2, Math<R>::lg2(fmax(a2, Tiny<R>::v)), A.ent);
-    A.cnt += (a2 > lo2 && a2 < hi2) ? 1u : 0u;
-    A.gap = fmax(A.gap, a2 <= lo2 ? a2 : R(-1));
-}
-
-// Both magnitudes carried by each point G of the half-size spectrum:
-// x = 0: |Re G + Im G|, |Re G - Im G|;  x != 0: 2|Re G|, 2|Im G|.
+// Reductions over the thread's points.  Each point carries two magnitudes:
+// x = 0: |Re G + Im G|, |Re G - Im G|;  x != 0: 2|Re G|, 2|Im G|.  For x != 0 the
+// squares are accumulated as t = (Re G)^2 and scaled by the exact factor 4 at the
+// end (|F|^2 log2 |F|^2 = 4 t log2 t + 8 t).  Per square: moments up to MOM, the
+// Shannon term (values below Math::tiny contribute < 1e-28) and the running
+// maximum.  The nullity test (1-eps)^2 < |F|^2 < (1+eps)^2 and the gap (largest
+// |F|^2 below (1-eps)^2) only need a second look when the maximum exceeds
+// (1-eps)^2, which is rare outside stabilizer-like families.
 template <typename R, int RL, int MOM>
-__device__ __forceinline__ void acc_points(Acc<R>& A, const R (&re)[1 << RL], const R (&im)[1 << RL], bool x0, R lo2,
-                                           R hi2) {
+__device__ __forceinline__ AccD reduce_points(const R (&re)[1 << RL], const R (&im)[1 << RL], bool x0, R eps) {
+    R s1 = R(0), s2 = R(0), s3 = R(0), s4 = R(0), ent = R(0), mx = R(0);
+    auto acc = [&](R t) {
+        s1 += t;
+        const R t2 = t * t;
+        s2 += t2;
+        if constexpr (MOM >= 3) s3 = fma(t2, t, s3);
+        if constexpr (MOM >= 4) s4 = fma(t2, t2, s4);
+        ent = fma(t, Math<R>::lg2(fmax(t, Math<R>::tiny)), ent);
+        mx = fmax(mx, t);
+    };
     if (x0) {
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
             const R u = re[j] + im[j], v = re[j] - im[j];
-            acc_sq<R, MOM>(A, u * u, lo2, hi2);
-            acc_sq<R, MOM>(A, v * v, lo2, hi2);
+            acc(u * u);
+            acc(v * v);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
-            const R u = re[j] + re[j], v = im[j] + im[j];
-            acc_sq<R, MOM>(A, u * u, lo2, hi2);
-            acc_sq<R, MOM>(A, v * v, lo2, hi2);
+            acc(re[j] * re[j]);
+            acc(im[j] * im[j]);
         }
     }
+    const R sc = x0 ? R(1) : R(4);
+    const R lo2 = (R(1) - eps) * (R(1) - eps) / sc, hi2 = (R(1) + eps) * (R(1) + eps) / sc;
+    unsigned cnt = 0u;
+    R gap = mx;
+    if (mx > lo2) {
+        gap = R(-1);
+        auto test = [&](R t) {
+            cnt += (t > lo2 && t < hi2) ? 1u : 0u;
+            gap = fmax(gap, t <= lo2 ? t : R(-1));
+        };
+        if (x0) {
+#pragma unroll
+            for (int j = 0; j < (1 << RL); ++j) {
+                const R u = re[j] + im[j], v = re[j] - im[j];
+                test(u * u);
+                test(v * v);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < (1 << RL); ++j) {
+                test(re[j] * re[j]);
+                test(im[j] * im[j]);
+            }
+        }
+    }
+    AccD d;
+    const double scd = (double)sc;
+    d.s1 = scd * (double)s1;
+    d.s2 = scd * scd * (double)s2;
+    d.s3 = scd * scd * scd * (double)s3;
+    d.s4 = scd * scd * scd * scd * (double)s4;
+    d.ent = x0 ? (double)ent : 4.0 * (double)ent + 8.0 * (double)s1;
+    d.gap = gap >= R(0) ? scd * (double)gap : -1.0;
+    d.cnt = cnt;
+    return d;
 }
 
 __device__ __forceinline__ void add_to(AccD& a, const AccD& b) {
@@ -216,10 +283,21 @@ __device__ __forceinline__ AccD wave_reduce(AccD a) {
     return a;
 }
 
-// Fixed-order workgroup reduction; the total is valid in thread 0.
-template <int NT>
+// Fixed-order workgroup reduction; the total is valid in thread 0.  Each wave
+// first reduces by shuffles over the values in use (moments up to MOM).
+template <int NT, int MOM>
 __device__ AccD block_reduce(AccD a, AccD* sh) {
-    a = wave_reduce<(NT < 64 ? NT : 64)>(a);
+    constexpr int WS = NT < 64 ? NT : 64;
+#pragma unroll
+    for (int off = WS / 2; off > 0; off >>= 1) {
+        a.s1 += __shfl_xor(a.s1, off);
+        a.ent += __shfl_xor(a.ent, off);
+        a.s2 += __shfl_xor(a.s2, off);
+        if constexpr (MOM >= 3) a.s3 += __shfl_xor(a.s3, off);
+        if constexpr (MOM >= 4) a.s4 += __shfl_xor(a.s4, off);
+        a.gap = fmax(a.gap, __shfl_xor(a.gap, off));
+        a.cnt += __shfl_xor(a.cnt, off);
+    }
     if constexpr (NT > 64) {
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         if (lane == 0) sh[wid] = a;
@@ -233,20 +311,7 @@ __device__ AccD block_reduce(AccD a, AccD* sh) {
     return a;
 }
 
-template <typename R>
-__device__ __forceinline__ AccD widen(const Acc<R>& a) {
-    AccD d;
-    d.s1 = (double)a.s1;
-    d.ent = (double)a.ent;
-    d.s2 = (double)a.s2;
-    d.s3 = (double)a.s3;
-    d.s4 = (double)a.s4;
-    d.gap = (double)a.gap;
-    d.cnt = a.cnt;
-    return d;
-}
-
-// Raw per-workgroup sums, stored in the FamilyRes layout.
+// Raw per-workgroup sums, stored in the FamilyRes layout (gap as |F|^2).
 __device__ __forceinline__ FamilyRes raw_res(const AccD& a, uint64_t x) {
     FamilyRes r;
     r.x = x;
@@ -288,12 +353,6 @@ __device__ __forceinline__ FamilyRes finish(const AccD& a, uint64_t x, int n) {
     return r;
 }
 
-template <typename R>
-__device__ __forceinline__ void thresholds(R eps, R& lo2, R& hi2) {
-    lo2 = (R(1) - eps) * (R(1) - eps);
-    hi2 = (R(1) + eps) * (R(1) + eps);
-}
-
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
@@ -311,14 +370,22 @@ k_fused(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     const uint64_t x = xs ? xs[slot] : x0 + slot;
     R re[1 << RL], im[1 << RL];
     load_products<R, TL, RL>(psi, n - 1, (uint32_t)x, 0u, re, im);
-    tile_fwht<R, TL, RL>(re, im, lds, 0);
-    R lo2, hi2;
-    thresholds(eps, lo2, hi2);
-    Acc<R> acc;
-    acc.init();
-    acc_points<R, RL, MOM>(acc, re, im, x == 0, lo2, hi2);
-    const AccD tot = block_reduce<NT>(widen(acc), shw);
+    tile_fwht<R, TL, RL, 0>(re, im, lds);
+    const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
     if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, n);
+}
+
+template <typename R, int TL, int RL>
+__device__ __forceinline__ void store_tile(cx<R>* __restrict__ dst, const R (&re)[1 << RL], const R (&im)[1 << RL]) {
+    constexpr int A = final_window<TL, RL, 0>();
+    cx<R>* p = dst + thread_part<A, RL>(threadIdx.x);
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) {
+        cx<R> v;
+        v.re = re[j];
+        v.im = im[j];
+        p[(uint32_t)j << A] = v;
+    }
 }
 
 // First pass of a multi-pass transform: products + low K index bits of one tile.
@@ -331,66 +398,116 @@ k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     __shared__ cx<R> lds[Lds<K>::elems];
     const int nh = n - 1;
     const uint32_t tile = blockIdx.x, slot = blockIdx.y;
-    const uint64_t x = xs ? xs[slot] : x0 + slot;
+    const uint32_t x = (uint32_t)(xs ? xs[slot] : x0 + slot);
     R re[1 << RL], im[1 << RL];
-    load_products<R, TL, RL>(psi, nh, (uint32_t)x, tile, re, im);
-    const int a = tile_fwht<R, TL, RL>(re, im, lds, 0);
-    cx<R>* dst = work + ((size_t)slot << nh) + ((size_t)tile << K);
+    if (x >= (1u << K)) load_products_hi<R, TL, RL>(psi, x, tile, re, im);
+    else load_products<R, TL, RL>(psi, nh, x, tile, re, im);
+    tile_fwht<R, TL, RL, 0>(re, im, lds);
+    store_tile<R, TL, RL>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
+}
+
+// First pass for a run of consecutive families x0 + i that share x >> K != 0
+// (exact sweeps): the state tile tu << K and its partner (tu ^ (x >> K)) << K
+// are the same for the whole run, so a workgroup loads them once (own tile in
+// registers, partner tile in LDS) and forms, transforms and writes `fam`
+// families in turn.  The partner tile is stored with its register-block index
+// XORed by (x mod 2^K) >> TL, constant over the run, so that every family reads
+// it at a per-thread base plus immediate offsets.  Grid: (tiles, run / fam).
+template <typename R, int TL, int RL>
+__global__ void __launch_bounds__(1 << TL)
+k_first_shared(const cx<R>* __restrict__ psi, int n, uint64_t x0, int fam, cx<R>* __restrict__ work) {
+    constexpr int K = TL + RL;
+    __shared__ cx<R> vt[1 << K];
+    __shared__ cx<R> lds[Lds<K>::elems];
+    const int nh = n - 1;
+    const uint32_t tile = blockIdx.x, grp = blockIdx.y;
+    const uint32_t slot0 = grp * (uint32_t)fam;
+    const uint32_t xr = (uint32_t)(x0 + slot0);
+    const uint32_t xh = xr >> K;
+    const int q = 31 - __builtin_clz(xh);
+    const uint32_t lowm = (1u << q) - 1u;
+    const uint32_t tu = (tile & lowm) | ((tile & ~lowm) << 1);
+    const uint32_t tv = tu ^ xh;
+    const uint32_t jx = (xr & ((1u << K) - 1u)) >> TL;
+    const uint32_t tid = threadIdx.x;
+    R ur[1 << RL], ui[1 << RL];
+    {
+        const cx<R>* pa = psi + ((size_t)tu << K) + tid;
+        const cx<R>* pv = psi + ((size_t)tv << K) + tid;
 #pragma unroll
-    for (int j = 0; j < (1 << RL); ++j) {
-        cx<R> v;
-        v.re = re[j];
-        v.im = im[j];
-        dst[win_idx(threadIdx.x, j, a, RL)] = v;
+        for (int j = 0; j < (1 << RL); ++j) {
+            const cx<R> u = pa[(uint32_t)j << TL];
+            ur[j] = u.re;
+            ui[j] = u.im;
+            vt[tid + (((uint32_t)j ^ jx) << TL)] = pv[(uint32_t)j << TL];
+        }
+    }
+    __syncthreads();
+    for (int f = 0; f < fam; ++f) {
+        const uint32_t slot = slot0 + (uint32_t)f;
+        const uint32_t xlo = (uint32_t)(x0 + slot) & ((1u << TL) - 1u);
+        const cx<R>* pv = vt + (tid ^ xlo);
+        R re[1 << RL], im[1 << RL];
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) {
+            const cx<R> v = pv[(uint32_t)j << TL];
+            re[j] = ur[j] * v.re + ui[j] * v.im;
+            im[j] = ur[j] * v.im - ui[j] * v.re;
+        }
+        tile_fwht<R, TL, RL, 0>(re, im, lds);
+        store_tile<R, TL, RL>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
     }
 }
 
-// Column pass over index bits [lo, lo + s) of every family in the batch.
-// A tile is 2^s rows (stride 2^lo) by 2^w consecutive columns, w = K - s.
+// Column pass over index bits [lo, lo + S) of every family in the batch.
+// A tile is 2^S rows (stride 2^lo) by 2^W consecutive columns, W = K - S.
 // Grid: (2^(nh - K), families).  LAST: reduce to one partial per workgroup
 // (parts[family][block]) instead of writing the spectrum back.
-template <typename R, int TL, int RL, bool LAST, int MOM>
+template <typename R, int TL, int RL, int S, bool LAST, int MOM>
 __global__ void __launch_bounds__(1 << TL)
-k_column(cx<R>* __restrict__ work, int n, int lo, int s, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
+k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
          FamilyRes* __restrict__ parts) {
     constexpr int K = TL + RL;
     constexpr int NT = 1 << TL;
+    constexpr int W = K - S;
     __shared__ cx<R> lds[Lds<K>::elems];
     const int nh = n - 1;
-    const int w = K - s;
-    const int cbits = lo - w;
+    const int cbits = lo - W;
     const uint32_t bid = blockIdx.x, slot = blockIdx.y;
     const uint32_t cb = bid & ((1u << cbits) - 1u);
     const uint32_t hb = bid >> cbits;
-    cx<R>* base = work + ((size_t)slot << nh) + ((size_t)hb << (lo + s)) + ((size_t)cb << w);
-    const uint32_t wmask = (1u << w) - 1u;
+    cx<R>* base = work + ((size_t)slot << nh) + ((size_t)hb << (lo + S)) + ((size_t)cb << W);
+    const uint32_t tid = threadIdx.x;
+    constexpr uint32_t WM = (1u << W) - 1u;
+    // Point i = T | J (thread part T, register part J = j 2^A, disjoint bits) sits at
+    // column i mod 2^W and row i >> W: a per-thread base plus, for each j, a
+    // compile-time column offset and a compile-time number of rows.
+    const cx<R>* pin = base + (tid & WM) + ((size_t)(tid >> W) << lo);
     R re[1 << RL], im[1 << RL];
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) {
-        const uint32_t i = threadIdx.x + ((uint32_t)j << TL);
-        const cx<R> v = base[(i & wmask) + ((size_t)(i >> w) << lo)];
+        const uint32_t J = (uint32_t)j << TL;
+        const cx<R> v = pin[(J & WM) + ((size_t)(J >> W) << lo)];
         re[j] = v.re;
         im[j] = v.im;
     }
-    const int a = tile_fwht<R, TL, RL>(re, im, lds, w);
+    tile_fwht<R, TL, RL, W>(re, im, lds);
     if constexpr (!LAST) {
+        constexpr int A = final_window<TL, RL, W>();
+        const uint32_t T = thread_part<A, RL>(tid);
+        cx<R>* pout = base + (T & WM) + ((size_t)(T >> W) << lo);
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
-            const uint32_t i = win_idx(threadIdx.x, j, a, RL);
+            const uint32_t J = (uint32_t)j << A;
             cx<R> v;
             v.re = re[j];
             v.im = im[j];
-            base[(i & wmask) + ((size_t)(i >> w) << lo)] = v;
+            pout[(J & WM) + ((size_t)(J >> W) << lo)] = v;
         }
     } else {
         __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
         const uint64_t x = xs ? xs[slot] : x0 + slot;
-        R lo2, hi2;
-        thresholds(eps, lo2, hi2);
-        Acc<R> acc;
-        acc.init();
-        acc_points<R, RL, MOM>(acc, re, im, x == 0, lo2, hi2);
-        const AccD tot = block_reduce<NT>(widen(acc), shw);
+        const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
         if (threadIdx.x == 0) parts[(size_t)slot * gridDim.x + bid] = raw_res(tot, x);
     }
 }
@@ -409,16 +526,31 @@ k_finalize(const FamilyRes* __restrict__ parts, int nblk, int n, FamilyRes* __re
     if (threadIdx.x == 0) out[blockIdx.x] = finish<MOM>(a, p[0].x, n);
 }
 
+__device__ __forceinline__ void zero_sums(SweepSums& t) {
+    t.S[0] = t.S[1] = t.S[2] = t.L = t.P = 0.0;
+    t.gap = -1.0;
+    t.nu_cnt = 0;
+    t.count = 0;
+}
+
+__device__ __forceinline__ void add_sums(SweepSums& a, const SweepSums& b) {
+    a.S[0] += b.S[0];
+    a.S[1] += b.S[1];
+    a.S[2] += b.S[2];
+    a.L += b.L;
+    a.P += b.P;
+    a.gap = fmax(a.gap, b.gap);
+    a.nu_cnt += b.nu_cnt;
+    a.count += b.count;
+}
+
 // Fixed-order sum of count per-family results into one SweepSums.
 __global__ void __launch_bounds__(256)
 k_reduce_fam(const FamilyRes* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
     constexpr int NT = 256;
     __shared__ SweepSums sh[NT];
     SweepSums t;
-    t.S[0] = t.S[1] = t.S[2] = t.L = t.P = 0.0;
-    t.gap = -1.0;
-    t.nu_cnt = 0;
-    t.count = 0;
+    zero_sums(t);
     for (int64_t i = threadIdx.x; i < count; i += NT) {
         const FamilyRes v = in[i];
         t.S[0] += v.m[0];
@@ -433,18 +565,23 @@ k_reduce_fam(const FamilyRes* __restrict__ in, int64_t count, SweepSums* __restr
     sh[threadIdx.x] = t;
     __syncthreads();
     for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            SweepSums& a = sh[threadIdx.x];
-            const SweepSums& b = sh[threadIdx.x + h];
-            a.S[0] += b.S[0];
-            a.S[1] += b.S[1];
-            a.S[2] += b.S[2];
-            a.L += b.L;
-            a.P += b.P;
-            a.gap = fmax(a.gap, b.gap);
-            a.nu_cnt += b.nu_cnt;
-            a.count += b.count;
-        }
+        if ((int)threadIdx.x < h) add_sums(sh[threadIdx.x], sh[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_reduce_sweep(const SweepSums* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
+    constexpr int NT = 256;
+    __shared__ SweepSums sh[NT];
+    SweepSums t;
+    zero_sums(t);
+    for (int64_t i = threadIdx.x; i < count; i += NT) add_sums(t, in[i]);
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) add_sums(sh[threadIdx.x], sh[threadIdx.x + h]);
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = sh[0];
@@ -473,52 +610,11 @@ __global__ void k_signed(const cx<R>* __restrict__ G, int n, uint32_t x, double*
     c[z] = v;
 }
 
-__global__ void __launch_bounds__(256)
-k_reduce_sweep(const SweepSums* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
-    constexpr int NT = 256;
-    __shared__ SweepSums sh[NT];
-    SweepSums t;
-    t.S[0] = t.S[1] = t.S[2] = t.L = t.P = 0.0;
-    t.gap = -1.0;
-    t.nu_cnt = 0;
-    t.count = 0;
-    for (int64_t i = threadIdx.x; i < count; i += NT) {
-        const SweepSums v = in[i];
-        t.S[0] += v.S[0];
-        t.S[1] += v.S[1];
-        t.S[2] += v.S[2];
-        t.L += v.L;
-        t.P += v.P;
-        t.gap = fmax(t.gap, v.gap);
-        t.nu_cnt += v.nu_cnt;
-        t.count += v.count;
-    }
-    sh[threadIdx.x] = t;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            SweepSums& a = sh[threadIdx.x];
-            const SweepSums& b = sh[threadIdx.x + h];
-            a.S[0] += b.S[0];
-            a.S[1] += b.S[1];
-            a.S[2] += b.S[2];
-            a.L += b.L;
-            a.P += b.P;
-            a.gap = fmax(a.gap, b.gap);
-            a.nu_cnt += b.nu_cnt;
-            a.count += b.count;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = sh[0];
-}
-
-// Tile shapes: first pass K = 12 (256 threads x 16 points); column passes K = 13
-// single (512 x 16) / 12 double (256 x 16); fused kernels K = n - 1.
+// Tile shapes: first pass and column passes K = 12 (256 threads x 16 points,
+// 35 KB (single) / 70 KB (double) of LDS); single-precision column passes use
+// K = 13 (512 x 16, 70 KB) when that saves a pass; fused kernels K = n - 1.
 constexpr int K_FIRST = 12;
-template <typename R> struct ColShape;
-template <> struct ColShape<float> { static constexpr int TL = 9, RL = 4; };
-template <> struct ColShape<double> { static constexpr int TL = 8, RL = 4; };
+constexpr int COL_RL = 4;
 
 template <typename R, int K, int MOM>
 hipError_t launch_fused_k(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
@@ -547,6 +643,32 @@ hipError_t launch_fused(const void* psi, int n, const uint64_t* xs, uint64_t x0,
     }
 }
 
+template <typename R, int TL, bool LAST, int MOM>
+hipError_t launch_column_t(int s, dim3 grid, cx<R>* work, int n, int lo, const uint64_t* xs, uint64_t x0, R eps,
+                           FamilyRes* parts, hipStream_t st) {
+    switch (s) {
+#define PW_COL(S)                                                                                                   \
+    case S:                                                                                                         \
+        hipLaunchKernelGGL((k_column<R, TL, COL_RL, S, LAST, MOM>), grid, dim3(1 << TL), 0, st, work, n, lo, xs, x0, \
+                           eps, parts);                                                                             \
+        return hipGetLastError();
+        PW_COL(1) PW_COL(2) PW_COL(3) PW_COL(4) PW_COL(5) PW_COL(6) PW_COL(7) PW_COL(8) PW_COL(9)
+#undef PW_COL
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, bool LAST, int MOM>
+hipError_t launch_column(int ktile, int s, int nh, int nb, cx<R>* work, int n, int lo, const uint64_t* xs,
+                         uint64_t x0, R eps, FamilyRes* parts, hipStream_t st) {
+    const dim3 grid(1u << (nh - ktile), nb);
+    if constexpr (sizeof(R) == 4) {
+        if (ktile == 13) return launch_column_t<R, 9, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st);
+    }
+    if (ktile != 12) return hipErrorInvalidValue;
+    return launch_column_t<R, 8, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st);
+}
+
 template <typename R, int MOM>
 hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, double eps,
                         void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st, const LaunchTimer* tm) {
@@ -558,36 +680,38 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
         if (tm) tm->end(tm->self, 0, nb, st);
         return err;
     }
-    constexpr int TL = ColShape<R>::TL, RL = ColShape<R>::RL;
+    const uint32_t tiles = 1u << (P.nh - K_FIRST);
     if (tm) tm->begin(tm->self, 1, st);
-    hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (P.nh - K_FIRST), nb), dim3(256), 0, st, (const cx<R>*)psi,
-                       P.n, xs, x0, (cx<R>*)work);
+    if (!xs && x0 >= (1ull << K_FIRST) && (x0 >> 8) == ((x0 + nb - 1) >> 8) && (x0 % nb) == 0) {
+        // a run of consecutive families inside one 256-aligned block: share the state tiles
+        int fam = 1;
+        while (fam < 16 && (nb % (2 * fam)) == 0 && (uint64_t)tiles * (nb / (2 * fam)) >= 1024) fam *= 2;
+        hipLaunchKernelGGL((k_first_shared<R, 8, 4>), dim3(tiles, nb / fam), dim3(256), 0, st, (const cx<R>*)psi,
+                           P.n, x0, fam, (cx<R>*)work);
+    } else {
+        hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(tiles, nb), dim3(256), 0, st, (const cx<R>*)psi, P.n, xs, x0,
+                           (cx<R>*)work);
+    }
     if (tm) tm->end(tm->self, 1, nb, st);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    const dim3 grid(1u << (P.nh - (TL + RL)), nb);
     for (int i = 0; i < P.npass; ++i) {
         const bool last = i + 1 == P.npass;
         if (tm) tm->begin(tm->self, last ? 3 : 2, st);
-        if (!last) {
-            hipLaunchKernelGGL((k_column<R, TL, RL, false, MOM>), grid, dim3(1 << TL), 0, st, (cx<R>*)work, P.n,
-                               P.lo[i], P.s[i], xs, x0, e, parts);
-        } else {
-            hipLaunchKernelGGL((k_column<R, TL, RL, true, MOM>), grid, dim3(1 << TL), 0, st, (cx<R>*)work, P.n,
-                               P.lo[i], P.s[i], xs, x0, e, parts);
-        }
+        err = last ? launch_column<R, true, MOM>(P.ktile, P.s[i], P.nh, nb, (cx<R>*)work, P.n, P.lo[i], xs, x0, e,
+                                                 parts, st)
+                   : launch_column<R, false, 2>(P.ktile, P.s[i], P.nh, nb, (cx<R>*)work, P.n, P.lo[i], xs, x0, e,
+                                                parts, st);
         if (tm) tm->end(tm->self, last ? 3 : 2, nb, st);
-        err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, (int)grid.x, P.n, out);
+    hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* work, hipStream_t st) {
     // the multi-pass schedule without the final reduction
-    constexpr int TL = ColShape<R>::TL, RL = ColShape<R>::RL;
     const int nh = P.nh;
     if (P.fused || nh <= K_FIRST) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (nh - K_FIRST), 1), dim3(256), 0, st, (const cx<R>*)psi, P.n,
@@ -595,10 +719,8 @@ hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* wor
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
-        hipLaunchKernelGGL((k_column<R, TL, RL, false, 2>), dim3(1u << (nh - (TL + RL)), 1), dim3(1 << TL), 0, st,
-                           (cx<R>*)work, P.n, P.lo[i], P.s[i], (const uint64_t*)nullptr, x, (R)0,
-                           (FamilyRes*)nullptr);
-        err = hipGetLastError();
+        err = launch_column<R, false, 2>(P.ktile, P.s[i], nh, 1, (cx<R>*)work, P.n, P.lo[i], (const uint64_t*)nullptr,
+                                         x, (R)0, (FamilyRes*)nullptr, st);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -611,8 +733,6 @@ Plan make_plan(int n, bool dbl) {
     P.n = n;
     P.nh = n - 1;
     const int fmax = dbl ? 12 : 13;
-    const int ktile = dbl ? 12 : 13;
-    const int smax = dbl ? 9 : 9;  // keeps columns >= 128 bytes
     if (P.nh <= fmax) {
         P.fused = true;
         P.k1 = P.nh;
@@ -623,6 +743,15 @@ Plan make_plan(int n, bool dbl) {
     P.fused = false;
     P.k1 = K_FIRST;
     const int rem = P.nh - K_FIRST;
+    // column tiles of 2^ktile points with rows of >= 128 bytes: s <= ktile - 4 (single),
+    // ktile - 3 (double); single precision takes 13-bit tiles when that saves a pass
+    int ktile = 12;
+    int smax = dbl ? 9 : 8;
+    if (!dbl && (rem + 7) / 8 > (rem + 8) / 9) {
+        ktile = 13;
+        smax = 9;
+    }
+    P.ktile = ktile;
     const int np = (rem + smax - 1) / smax;
     P.npass = np;
     int lo = K_FIRST;
