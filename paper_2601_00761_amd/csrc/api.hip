@@ -131,8 +131,6 @@ struct pw_ctx_s {
         hipEvent_t a, b;
         int kclass, families;
     };
-    bool active[4] = {false, false, false, false};
-    hipEvent_t open_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<Pair> pending;
     std::vector<hipEvent_t> pool;
     double total_ms[4] = {0, 0, 0, 0};
@@ -154,34 +152,24 @@ hipEvent_t take_event(pw_ctx c) {
     return e;
 }
 
-void timer_begin(void* self, int k, hipStream_t st) {
+bool timer_take(void* self, int k, hipEvent_t* a, hipEvent_t* b) {
     pw_ctx c = (pw_ctx)self;
-    if (c->launches[k]++ % (uint64_t)c->timing_every != 0) return;
-    hipEvent_t a = take_event(c);
-    if (!a) return;
-    if (hipEventRecord(a, st) != hipSuccess) {
-        c->pool.push_back(a);
-        return;
+    if (c->launches[k]++ % (uint64_t)c->timing_every != 0) return false;
+    hipEvent_t e0 = take_event(c);
+    if (!e0) return false;
+    hipEvent_t e1 = take_event(c);
+    if (!e1) {
+        c->pool.push_back(e0);
+        return false;
     }
-    c->open_ev[k] = a;
-    c->active[k] = true;
+    *a = e0;
+    *b = e1;
+    return true;
 }
 
-void timer_end(void* self, int k, int families, hipStream_t st) {
+void timer_commit(void* self, int k, int families, hipEvent_t a, hipEvent_t b) {
     pw_ctx c = (pw_ctx)self;
-    if (!c->active[k]) return;
-    c->active[k] = false;
-    hipEvent_t b = take_event(c);
-    if (!b) {
-        c->pool.push_back(c->open_ev[k]);
-        return;
-    }
-    if (hipEventRecord(b, st) != hipSuccess) {
-        c->pool.push_back(c->open_ev[k]);
-        c->pool.push_back(b);
-        return;
-    }
-    c->pending.push_back({c->open_ev[k], b, k, families});
+    c->pending.push_back({a, b, k, families});
 }
 
 const LaunchTimer* timer_of(pw_ctx c) { return c->timing_every > 0 ? &c->timer : nullptr; }
@@ -310,8 +298,8 @@ pw_status pw_ctx_create(pw_ctx* out, int device, void* hip_stream) {
     pw_ctx c = new pw_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    c->timer.begin = timer_begin;
-    c->timer.end = timer_end;
+    c->timer.take = timer_take;
+    c->timer.commit = timer_commit;
     c->timer.self = c;
     *out = c;
     g_err.clear();
@@ -635,10 +623,7 @@ pw_status pw_timing_enable(pw_ctx c, int every) {
     if (s != PW_OK) return s;
     if (every < 0) return fail(PW_ERR_ARG, "every must be >= 0");
     c->timing_every = every;
-    for (int k = 0; k < 4; ++k) {
-        c->launches[k] = 0;
-        c->active[k] = false;
-    }
+    for (int k = 0; k < 4; ++k) c->launches[k] = 0;
     return PW_OK;
 }
 

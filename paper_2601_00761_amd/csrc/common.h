@@ -53,12 +53,14 @@ struct Plan {
 
 Plan make_plan(int n, bool dbl);
 
-// Optional hook around kernel launches, used to time launches with HIP events
-// on the launch stream.  Kernel classes: 0 fused, 1 first pass, 2 middle column
+// Optional launch timing.  For a sampled launch, take() hands out two HIP events
+// that the launch attaches to the kernel's own dispatch (hipExtLaunchKernel start
+// and stop events, i.e. the kernel's execution interval on its stream), and
+// commit() files them.  Kernel classes: 0 fused, 1 first pass, 2 middle column
 // pass, 3 final column pass.
 struct LaunchTimer {
-    void (*begin)(void* self, int kclass, hipStream_t st);
-    void (*end)(void* self, int kclass, int families, hipStream_t st);
+    bool (*take)(void* self, int kclass, hipEvent_t* start, hipEvent_t* stop);
+    void (*commit)(void* self, int kclass, int families, hipEvent_t start, hipEvent_t stop);
     void* self;
 };
 

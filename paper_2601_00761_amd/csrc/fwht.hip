@@ -23,6 +23,7 @@
 // spectrum back.  Per-workgroup FP64 partials are summed per family in a fixed
 // order by a separate finalize kernel, so results are bitwise reproducible.
 #include "common.h"
+#include <hip/hip_ext.h>
 #include <math.h>
 
 namespace pw {
@@ -610,6 +611,15 @@ __global__ void k_signed(const cx<R>* __restrict__ G, int n, uint32_t x, double*
     c[z] = v;
 }
 
+// Launch with optional timing events attached to the dispatch itself.
+#define PW_LAUNCH(TM, KC, NB, KERNEL, GRID, BLOCK, ST, ...)                                      \
+    do {                                                                                        \
+        hipEvent_t ev0_ = nullptr, ev1_ = nullptr;                                              \
+        const bool smp_ = (TM) != nullptr && (TM)->take((TM)->self, (KC), &ev0_, &ev1_);        \
+        hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, ST, ev0_, ev1_, 0u, __VA_ARGS__);          \
+        if (smp_) (TM)->commit((TM)->self, (KC), (NB), ev0_, ev1_);                             \
+    } while (0)
+
 // Tile shapes: first pass and column passes K = 12 (256 threads x 16 points,
 // 35 KB (single) / 70 KB (double) of LDS); single-precision column passes use
 // K = 13 (512 x 16, 70 KB) when that saves a pass; fused kernels K = n - 1.
@@ -618,26 +628,26 @@ constexpr int COL_RL = 4;
 
 template <typename R, int K, int MOM>
 hipError_t launch_fused_k(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
-                          hipStream_t st) {
+                          hipStream_t st, const LaunchTimer* tm) {
     constexpr int RL0 = K < 4 ? K : 4;
     constexpr int TL = K == 13 ? 9 : K - RL0;
     constexpr int RL = K - TL;
-    hipLaunchKernelGGL((k_fused<R, TL, RL, MOM>), dim3(nb), dim3(1 << TL), 0, st, (const cx<R>*)psi, n, xs, x0, eps,
-                       out);
+    PW_LAUNCH(tm, 0, nb, (k_fused<R, TL, RL, MOM>), dim3(nb), dim3(1 << TL), st, (const cx<R>*)psi, n, xs, x0, eps,
+              out);
     return hipGetLastError();
 }
 
 template <typename R, int MOM>
 hipError_t launch_fused(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
-                        hipStream_t st) {
+                        hipStream_t st, const LaunchTimer* tm) {
     switch (n - 1) {
 #define PW_CASE(K) \
-    case K: return launch_fused_k<R, K, MOM>(psi, n, xs, x0, nb, eps, out, st);
+    case K: return launch_fused_k<R, K, MOM>(psi, n, xs, x0, nb, eps, out, st, tm);
         PW_CASE(0) PW_CASE(1) PW_CASE(2) PW_CASE(3) PW_CASE(4) PW_CASE(5) PW_CASE(6)
         PW_CASE(7) PW_CASE(8) PW_CASE(9) PW_CASE(10) PW_CASE(11) PW_CASE(12)
 #undef PW_CASE
         case 13:
-            if constexpr (sizeof(R) == 4) return launch_fused_k<R, 13, MOM>(psi, n, xs, x0, nb, eps, out, st);
+            if constexpr (sizeof(R) == 4) return launch_fused_k<R, 13, MOM>(psi, n, xs, x0, nb, eps, out, st, tm);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
@@ -645,12 +655,13 @@ hipError_t launch_fused(const void* psi, int n, const uint64_t* xs, uint64_t x0,
 
 template <typename R, int TL, bool LAST, int MOM>
 hipError_t launch_column_t(int s, dim3 grid, cx<R>* work, int n, int lo, const uint64_t* xs, uint64_t x0, R eps,
-                           FamilyRes* parts, hipStream_t st) {
+                           FamilyRes* parts, hipStream_t st, const LaunchTimer* tm) {
+    const int kc = LAST ? 3 : 2;
     switch (s) {
-#define PW_COL(S)                                                                                                   \
-    case S:                                                                                                         \
-        hipLaunchKernelGGL((k_column<R, TL, COL_RL, S, LAST, MOM>), grid, dim3(1 << TL), 0, st, work, n, lo, xs, x0, \
-                           eps, parts);                                                                             \
+#define PW_COL(S)                                                                                                    \
+    case S:                                                                                                          \
+        PW_LAUNCH(tm, kc, (int)grid.y, (k_column<R, TL, COL_RL, S, LAST, MOM>), grid, dim3(1 << TL), st, work, n, lo, \
+                  xs, x0, eps, parts);                                                                               \
         return hipGetLastError();
         PW_COL(1) PW_COL(2) PW_COL(3) PW_COL(4) PW_COL(5) PW_COL(6) PW_COL(7) PW_COL(8) PW_COL(9)
 #undef PW_COL
@@ -660,13 +671,13 @@ hipError_t launch_column_t(int s, dim3 grid, cx<R>* work, int n, int lo, const u
 
 template <typename R, bool LAST, int MOM>
 hipError_t launch_column(int ktile, int s, int nh, int nb, cx<R>* work, int n, int lo, const uint64_t* xs,
-                         uint64_t x0, R eps, FamilyRes* parts, hipStream_t st) {
+                         uint64_t x0, R eps, FamilyRes* parts, hipStream_t st, const LaunchTimer* tm) {
     const dim3 grid(1u << (nh - ktile), nb);
     if constexpr (sizeof(R) == 4) {
-        if (ktile == 13) return launch_column_t<R, 9, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st);
+        if (ktile == 13) return launch_column_t<R, 9, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st, tm);
     }
     if (ktile != 12) return hipErrorInvalidValue;
-    return launch_column_t<R, 8, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st);
+    return launch_column_t<R, 8, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st, tm);
 }
 
 template <typename R, int MOM>
@@ -674,35 +685,26 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
                         void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st, const LaunchTimer* tm) {
     if (nb <= 0) return hipSuccess;
     const R e = (R)eps;
-    if (P.fused) {
-        if (tm) tm->begin(tm->self, 0, st);
-        hipError_t err = launch_fused<R, MOM>(psi, P.n, xs, x0, nb, e, out, st);
-        if (tm) tm->end(tm->self, 0, nb, st);
-        return err;
-    }
+    if (P.fused) return launch_fused<R, MOM>(psi, P.n, xs, x0, nb, e, out, st, tm);
     const uint32_t tiles = 1u << (P.nh - K_FIRST);
-    if (tm) tm->begin(tm->self, 1, st);
     if (!xs && x0 >= (1ull << K_FIRST) && (x0 >> 8) == ((x0 + nb - 1) >> 8) && (x0 % nb) == 0) {
         // a run of consecutive families inside one 256-aligned block: share the state tiles
         int fam = 1;
         while (fam < 16 && (nb % (2 * fam)) == 0 && (uint64_t)tiles * (nb / (2 * fam)) >= 1024) fam *= 2;
-        hipLaunchKernelGGL((k_first_shared<R, 8, 4>), dim3(tiles, nb / fam), dim3(256), 0, st, (const cx<R>*)psi,
-                           P.n, x0, fam, (cx<R>*)work);
+        PW_LAUNCH(tm, 1, nb, (k_first_shared<R, 8, 4>), dim3(tiles, nb / fam), dim3(256), st, (const cx<R>*)psi, P.n,
+                  x0, fam, (cx<R>*)work);
     } else {
-        hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(tiles, nb), dim3(256), 0, st, (const cx<R>*)psi, P.n, xs, x0,
-                           (cx<R>*)work);
+        PW_LAUNCH(tm, 1, nb, (k_first<R, 8, 4>), dim3(tiles, nb), dim3(256), st, (const cx<R>*)psi, P.n, xs, x0,
+                  (cx<R>*)work);
     }
-    if (tm) tm->end(tm->self, 1, nb, st);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
         const bool last = i + 1 == P.npass;
-        if (tm) tm->begin(tm->self, last ? 3 : 2, st);
         err = last ? launch_column<R, true, MOM>(P.ktile, P.s[i], P.nh, nb, (cx<R>*)work, P.n, P.lo[i], xs, x0, e,
-                                                 parts, st)
+                                                 parts, st, tm)
                    : launch_column<R, false, 2>(P.ktile, P.s[i], P.nh, nb, (cx<R>*)work, P.n, P.lo[i], xs, x0, e,
-                                                parts, st);
-        if (tm) tm->end(tm->self, last ? 3 : 2, nb, st);
+                                                parts, st, tm);
         if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
@@ -720,7 +722,7 @@ hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* wor
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
         err = launch_column<R, false, 2>(P.ktile, P.s[i], nh, 1, (cx<R>*)work, P.n, P.lo[i], (const uint64_t*)nullptr,
-                                         x, (R)0, (FamilyRes*)nullptr, st);
+                                         x, (R)0, (FamilyRes*)nullptr, st, nullptr);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;

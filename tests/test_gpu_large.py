@@ -1,0 +1,112 @@
+"""Full-size checks (N = 26, 28, 30) through the C ABI.
+
+At these sizes the oracle cannot enumerate, so the checks use (a) the paper's
+closed forms for the product magic state |psi_m> = |T>^{N/2} |0>^{N/2}
+(Supplemental Material, Eq. sm-psi-m-m2x: m_{2;x} = 2^{-3N/2-k} when x_B = 0 and
+|x_A| = k, else 0), with p(x) = 2^{-N/2} [x_B = 0] (product of one-qubit marginals:
+1/2, 1/2 for |T>, 1, 0 for |0>) and nu_x = 2^{N/2} for x = 0, else 0;
+(b) Clifford invariance of M_2 (Clifford preconditioning section) through the
+Monte Carlo estimator at N = 28; (c) per-family oracle values on sampled x for a
+Haar state at N = 26.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from fp_bounds import family_bounds
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+pw = pytest.importorskip("paper_2601_00761_amd")
+
+
+def psi_m_sparse(n, dtype=np.complex64):
+    """|T>^{n/2} (qubits 0..n/2-1) |0>^{n/2}: 2^{n/2} nonzero amplitudes
+    2^{-n/4} e^{i pi/4 popcount(b)} at b < 2^{n/2}."""
+    h = n // 2
+    psi = np.zeros(1 << n, dtype=dtype)
+    b = np.arange(1 << h)
+    pc = np.array([bin(int(v)).count("1") for v in b])
+    psi[: 1 << h] = (2.0 ** (-h / 2)) * np.exp(1j * np.pi / 4 * pc)
+    return psi
+
+
+def psi_m_checks(n, g, xs):
+    h = n // 2
+    for i, x in enumerate(xs):
+        x = int(x)
+        xa, xb = x & ((1 << h) - 1), x >> h
+        k = bin(xa).count("1")
+        m2 = 0.0 if xb else 2.0 ** (-1.5 * n - k)
+        p = 0.0 if xb else 2.0 ** (-h)
+        scale = 2.0 ** (-1.5 * n)
+        assert abs(g["m"][i, 0] - m2) <= 2e-5 * max(m2, scale * 2.0 ** (-h)), (n, x, g["m"][i, 0], m2)
+        assert abs(g["p"][i] - p) <= 2e-5 * 2.0 ** (-h), (n, x, g["p"][i], p)
+        assert int(g["nu"][i]) == ((1 << (n - h)) if x == 0 else 0), (n, x, g["nu"][i])
+
+
+def _xs_for(n, seed):
+    h = n // 2
+    rnd = synth.splitmix64(seed, 0, 6) % np.uint64(1 << n)
+    lst = [0, 1, (1 << h) - 1, 0b1011 << 2, 1 << h, (1 << n) - 1, (1 << (n - 1)) | 5] + [int(v) for v in rnd]
+    return np.array(sorted(set(lst)), dtype=np.uint64)
+
+
+@pytest.mark.parametrize("n", [28, 30])
+def test_psi_m_closed_forms_full_size(n):
+    psi = psi_m_sparse(n)
+    xs = _xs_for(n, 1000 + n)
+    log("psi_m closed forms n=%d nx=%d" % (n, len(xs)))
+    ctx = pw.Context(0)
+    ctx.upload(psi, pw.PW_C64)
+    del psi
+    g = ctx.eval_x(xs, 1e-4)
+    ctx.close()
+    psi_m_checks(n, g, xs)
+
+
+def test_scrambled_psi_m_monte_carlo_n28():
+    # M_2(C psi_m) = M_2(psi_m) = (N/2) log2(4/3): preconditioning, marginal sampling and the estimator at full size
+    n = 28
+    psi = psi_m_sparse(n)
+    k, q, m = synth.gates_to_arrays(synth.random_brickwall_clifford(n, 2 * n, synth.SEED_BASE + 28))
+    log("scrambled psi_m MC n=%d gates=%d" % (n, len(k)))
+    ctx = pw.Context(0)
+    ctx.upload(psi, pw.PW_C64)
+    del psi
+    ctx.apply_gates(k, q, m)
+    res = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 64, 4097, 2e-3, 7)
+    ctx.close()
+    exact = (n // 2) * math.log2(4 / 3)
+    log("M2 = %.5f +- %.5f (exact %.5f), n_samples=%d" % (res["M"][0], res["M_se"][0], exact, res["n_samples"]))
+    assert res["M_se"][0] < 0.02
+    assert abs(res["M"][0] - exact) < 5 * res["M_se"][0] + 2e-3
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_haar_n26_sampled_families_vs_oracle(dtype):
+    n = 26
+    psi = synth.haar_state(n, synth.SEED_BASE + 26)
+    if dtype == pw.PW_C64:
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    xs = np.array([0, 3, 1 << 20, (1 << n) - 1], dtype=np.uint64)
+    log("haar n=%d dtype=%d" % (n, dtype))
+    ctx = pw.Context(0)
+    ctx.upload(psi, dtype)
+    g = ctx.eval_x(xs, 1e-7 if dtype == 0 else 1e-4)
+    ctx.close()
+    r = oracle.eval_x(psi, xs, eps=1e-7 if dtype == 0 else 1e-4, max_alpha=4)
+    for i, x in enumerate(xs):
+        if dtype == pw.PW_C128:
+            assert abs(g["m"][i, 0] / r["m"][i, 0] - 1) < 1e-10
+            assert abs(g["p"][i] / r["p"][i] - 1) < 1e-10
+            assert abs(g["ent"][i] / r["ent"][i] - 1) < 1e-10
+        else:
+            b = family_bounds(oracle.spectrum(psi, int(x)), n)
+            assert abs(g["m"][i, 0] - r["m"][i, 0]) <= b["m2"]
+            assert abs(g["p"][i] - r["p"][i]) <= b["p"]
+            assert abs(g["ent"][i] - r["ent"][i]) <= b["ent"]
+        assert int(g["nu"][i]) == int(r["nu"][i])
