@@ -106,6 +106,64 @@ def cpu_baseline(psi128, budget_s):
                       "with OpenMP inside each transform stage)" % (done - 1, n, done, 1 << n, el)}
 
 
+MC_N = 28
+MC_TARGET_SE = 1e-3
+MC_MAX = 16384
+MC_BATCH = 64
+
+
+def mc_leg(pw, torch, stream, eta, timing_every):
+    """M_2 wall time at fixed standard error: an N = 28 T-doped Clifford state (eta Cliffords
+    per T, N_T = 2N = 56, complex64), Clifford preconditioning with 2N brick-wall layers,
+    then x drawn from the exact marginal (plus x = 0), 64 per batch, until the standard
+    error of M_2 is 1e-3 or 16384 families.  Timed: preconditioning + sampling + evaluation.
+    State preparation (the T-doped circuit itself) is input generation and is not timed."""
+    import numpy as np
+    import synth
+    n = MC_N
+    seed = synth.SEED_BASE + 3 + 100 * eta
+    kinds, qubits, mats = synth.gates_to_arrays(synth.tdoped_stream(n, eta, 2 * n, seed))
+    pk, pq, pm = synth.gates_to_arrays(synth.random_brickwall_clifford(n, 2 * n, seed + 1))
+    psi0 = np.zeros(1 << n, dtype=np.complex64)
+    psi0[0] = 1.0
+    ctx = pw.Context(0, stream)
+    pw.pw_set_moments(ctx.h, 2)
+    ctx.upload(psi0, pw.PW_C64)
+    del psi0
+    ctx.apply_gates(kinds, qubits, mats)
+    torch.cuda.synchronize()
+    pw.pw_timing_enable(ctx.h, 1)
+    pw.pw_timing_reset(ctx.h)
+    t0 = time.perf_counter()
+    ctx.apply_gates(pk, pq, pm)
+    t1 = time.perf_counter()
+    res = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, MC_BATCH, MC_MAX + 1, MC_TARGET_SE, seed + 2)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    kt = {}
+    for k in range(4):
+        cnt, ms, fam = pw.pw_timing_read(ctx.h, k)
+        if cnt:
+            kt[KCLASS[k]] = dict(launches=cnt, avg_us=round(1e3 * ms / cnt, 2), families_per_launch=fam / cnt)
+    ctx.close()
+    fams = res["n_samples"]
+    # HBM roofline of the evaluation path: one read of psi (2^N x 8 B) per family is the
+    # algorithmic traffic; the path time per family is the sum of the kernel averages.
+    per_fam_us = sum(v["avg_us"] / v["families_per_launch"] for v in kt.values())
+    alg = float(1 << n) * 8.0
+    return {"workload": "N=%d T-doped Clifford state, eta=%d, N_T=%d, complex64; Clifford preconditioning %d "
+                        "brick-wall layers; x ~ exact marginal (x != 0) plus x = 0, %d per batch; stop at "
+                        "std-err(M_2) <= %g or %d families" % (n, eta, 2 * n, 2 * n, MC_BATCH, MC_TARGET_SE, MC_MAX),
+            "eta": eta, "M2": res["M"][0], "M2_se": res["M_se"][0], "M1": res["M1"], "M1_se": res["M1_se"],
+            "r2": res["r"][0], "n_samples": fams, "target_reached": bool(res["M_se"][0] <= MC_TARGET_SE),
+            "wall_s": t2 - t0, "precondition_s": t1 - t0, "mc_s": t2 - t1,
+            "pauli_strings_per_s_mc": fams * float(1 << n) / (t2 - t1),
+            "kernels": kt,
+            "roofline": {"bound": "hbm", "achieved": round(alg / (per_fam_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / (per_fam_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                         "note": "one read of psi per family over the summed kernel time of the path"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +173,9 @@ def main():
     ap.add_argument("--timing-every", type=int, default=16, help="time every k-th launch of each kernel class")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mc-leg", action="store_true", help="skip the N=28 Monte Carlo leg")
+    ap.add_argument("--mc-eta", type=int, nargs="+", default=[4],
+                    help="scrambling ratios of the N=28 Monte Carlo leg (the workload lists 1, 4 and 16)")
     ap.add_argument("--max-alpha", type=int, default=2, choices=(2, 4),
                     help="moments computed per family (the workload asks for M_1, M_2 and the nullity)")
     args = ap.parse_args()
@@ -231,6 +292,8 @@ def main():
         out["c128"] = {"value": args.steps_c128 * strings / el128, "ms_per_step": 1e3 * el128 / args.steps_c128,
                        "dtype": "f64", "M1": r128["M1"], "M2": r128["M"][0], "nullity": r128["nullity"],
                        "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0]}
+    if not args.no_mc_leg:
+        out["m2_wall_time"] = [mc_leg(pw, torch, stream, eta, args.timing_every) for eta in args.mc_eta]
     if not args.no_cpu_baseline:
         import oracle
         psi_host = psi128_dev.cpu().numpy()
