@@ -180,14 +180,56 @@ PW_API pw_status pw_exact(pw_ctx ctx, double eps, pw_result* out);
 PW_API pw_status pw_mc(pw_ctx ctx, pw_sampler sampler, double eps, int batch, uint64_t max_samples,
                 double target_se, uint64_t seed, pw_result* out);
 
+/* ---------------------------------------------------------------------------
+ * Learned proposal over X-bitstrings (not in the paper; an importance-sampling
+ * proposal for the Monte Carlo estimator).  A masked autoregressive network
+ * (MADE, Germain et al. 2015) n -> hidden -> hidden -> n with ReLU hidden layers,
+ * Bernoulli outputs and direct input->output links, FP32 on the device.  Bit i of
+ * x is input i; hidden unit k has degree (k mod (n-1)) + 1, so output i depends on
+ * bits j < i.  Parameters are a flat array (host side: doubles) in the layout
+ *   W1T[n*hidden] (i*hidden + k), b1[hidden], W2T[hidden*hidden] (kk*hidden + k),
+ *   b2[hidden], W3T[hidden*n] (kk*n + i), b3[n], AT[n*n] (j*n + i, used for j < i).
+ * The network lives in the context (library-owned device memory, freed at
+ * pw_ctx_destroy).  2 <= n <= 32, hidden in {64, 128, 256}.
+ * --------------------------------------------------------------------------- */
+PW_API pw_status pw_made_param_count(int n, int hidden, size_t* count);
+/* (Re)create the network with the given initial parameters (host array, copied) and
+ * reset the Adam state. */
+PW_API pw_status pw_made_init(pw_ctx ctx, int n, int hidden, const double* params);
+PW_API pw_status pw_made_get(pw_ctx ctx, double* params);
+/* log q(x) for the host list xs (host output, FP64 from FP32 logits). */
+PW_API pw_status pw_made_logq(pw_ctx ctx, const uint64_t* xs, int64_t count, double* logq);
+/* Loss -(sum_b w_b log q(x_b)) / sum_b w_b and its gradient (one batch, count <= 4096). */
+PW_API pw_status pw_made_grad(pw_ctx ctx, const uint64_t* xs, const double* w, int64_t count, double* loss,
+                              double* grad);
+/* Weighted maximum likelihood with Adam (beta1 0.9, beta2 0.999, eps 1e-8): `epochs`
+ * passes over the samples in minibatches, shuffled per epoch from `seed`.  Optional
+ * final_loss is the full-set loss after training. */
+PW_API pw_status pw_made_train(pw_ctx ctx, const uint64_t* xs, const double* w, int64_t count, int epochs,
+                               int minibatch, double lr, uint64_t seed, double* final_loss);
+/* Draws from q(x | x != 0): bit j of sample i compares u = (W0 >> 40) 2^-24 from
+ * Philox(ctr = (offset+i, attempt*64 + j, "MADE"), key = seed) with the logistic of
+ * output j (redraw when x = 0, at most 64 attempts; 0 is returned if all fail). */
+PW_API pw_status pw_made_sample(pw_ctx ctx, uint64_t seed, uint64_t offset, int64_t count, uint64_t* xs_out);
+/* Monte Carlo with the learned proposal: x = 0 evaluated; `pilot` draws from the exact
+ * marginal are evaluated and the network is trained on them with weights m_{2;x}/p(x)
+ * (targets the zero-variance proposal t(x) ~ m_{2;x}); then draws from the defensive
+ * mixture q = lambda p(.|x!=0) + (1-lambda) q_theta(.|x!=0) (per-sample choice from
+ * Philox stream "MIXC") are weighted exactly by m_{alpha;x}/q(x), until the standard
+ * error of M_2 is <= target_se or max_samples families (x = 0 included; pilot
+ * families not counted). */
+PW_API pw_status pw_mc_learned(pw_ctx ctx, double eps, int batch, uint64_t max_samples, double target_se,
+                               uint64_t seed, double lambda, int64_t pilot, int epochs, int minibatch, double lr,
+                               pw_result* out);
+
 /* Highest moment order computed per family: 4 (default: alpha = 2, 3, 4) or 2
  * (alpha = 2 only; m[1], m[2], S[1], S[2], M[1], M[2] are then NaN).  M_1, p(x)
  * and the nullity count are always computed. */
 PW_API pw_status pw_set_moments(pw_ctx ctx, int max_alpha);
 
-/* Measurement support.  pw_timing_enable(ctx, k) records a pair of HIP events on
- * the context stream around every k-th launch of each kernel class (k = 0
- * disables): class 0 = single-workgroup family kernel (small n), 1 = first
+/* Measurement support.  pw_timing_enable(ctx, k) attaches a pair of HIP events to
+ * the dispatch of every k-th launch of each kernel class (k = 0 disables; the
+ * events bracket the kernel's execution on the context stream): class 0 = single-workgroup family kernel (small n), 1 = first
  * transform pass (products + low 12 index bits), 2 = middle column pass,
  * 3 = final column pass with the reductions.  pw_timing_read synchronises the
  * recorded events and returns, for one class, the number of timed launches,

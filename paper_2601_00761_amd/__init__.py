@@ -20,7 +20,8 @@ __all__ = [
     "PWError", "PW_C128", "PW_C64", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
+    "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
 
@@ -98,6 +99,15 @@ def _load():
         "pw_exact": ([_vp, _dbl, ctypes.POINTER(pw_result)], _int),
         "pw_mc": ([_vp, _int, _dbl, _int, _u64, _dbl, _u64, ctypes.POINTER(pw_result)], _int),
         "pw_set_moments": ([_vp, _int], _int),
+        "pw_made_param_count": ([_int, _int, ctypes.POINTER(ctypes.c_size_t)], _int),
+        "pw_made_init": ([_vp, _int, _int, _vp], _int),
+        "pw_made_get": ([_vp, _vp], _int),
+        "pw_made_logq": ([_vp, _vp, _i64, _vp], _int),
+        "pw_made_grad": ([_vp, _vp, _vp, _i64, ctypes.POINTER(_dbl), _vp], _int),
+        "pw_made_train": ([_vp, _vp, _vp, _i64, _int, _int, _dbl, _u64, ctypes.POINTER(_dbl)], _int),
+        "pw_made_sample": ([_vp, _u64, _u64, _i64, _vp], _int),
+        "pw_mc_learned": ([_vp, _dbl, _int, _u64, _dbl, _u64, _dbl, _i64, _int, _int, _dbl,
+                           ctypes.POINTER(pw_result)], _int),
         "pw_timing_enable": ([_vp, _int], _int),
         "pw_timing_read": ([_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(_dbl), ctypes.POINTER(_u64)], _int),
         "pw_timing_reset": ([_vp], _int),
@@ -225,6 +235,63 @@ def pw_mc(ctx, sampler, eps, batch, max_samples, target_se, seed):
 
 def pw_set_moments(ctx, max_alpha):
     _check(_L.pw_set_moments(ctx, int(max_alpha)))
+
+
+def pw_made_param_count(n, hidden):
+    c = ctypes.c_size_t()
+    _check(_L.pw_made_param_count(int(n), int(hidden), ctypes.byref(c)))
+    return c.value
+
+
+def pw_made_init(ctx, n, hidden, params):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if p.size != pw_made_param_count(n, hidden):
+        raise ValueError("parameter array has the wrong size")
+    _check(_L.pw_made_init(ctx, int(n), int(hidden), p.ctypes.data))
+
+
+def pw_made_get(ctx, n, hidden):
+    out = np.empty(pw_made_param_count(n, hidden), dtype=np.float64)
+    _check(_L.pw_made_get(ctx, out.ctypes.data))
+    return out
+
+
+def pw_made_logq(ctx, xs):
+    xs = np.ascontiguousarray(xs, dtype=np.uint64)
+    out = np.empty(len(xs), dtype=np.float64)
+    _check(_L.pw_made_logq(ctx, xs.ctypes.data, len(xs), out.ctypes.data))
+    return out
+
+
+def pw_made_grad(ctx, xs, w, n, hidden):
+    xs = np.ascontiguousarray(xs, dtype=np.uint64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    g = np.empty(pw_made_param_count(n, hidden), dtype=np.float64)
+    loss = _dbl()
+    _check(_L.pw_made_grad(ctx, xs.ctypes.data, w.ctypes.data, len(xs), ctypes.byref(loss), g.ctypes.data))
+    return loss.value, g
+
+
+def pw_made_train(ctx, xs, w, epochs, minibatch, lr, seed):
+    xs = np.ascontiguousarray(xs, dtype=np.uint64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    loss = _dbl()
+    _check(_L.pw_made_train(ctx, xs.ctypes.data, w.ctypes.data, len(xs), int(epochs), int(minibatch), float(lr),
+                            int(seed), ctypes.byref(loss)))
+    return loss.value
+
+
+def pw_made_sample(ctx, seed, offset, count):
+    out = np.empty(int(count), dtype=np.uint64)
+    _check(_L.pw_made_sample(ctx, int(seed), int(offset), int(count), out.ctypes.data))
+    return out
+
+
+def pw_mc_learned(ctx, eps, batch, max_samples, target_se, seed, lam, pilot, epochs, minibatch, lr):
+    r = pw_result()
+    _check(_L.pw_mc_learned(ctx, float(eps), int(batch), int(max_samples), float(target_se), int(seed), float(lam),
+                            int(pilot), int(epochs), int(minibatch), float(lr), ctypes.byref(r)))
+    return r.as_dict()
 
 
 def pw_timing_enable(ctx, every):

@@ -3,6 +3,7 @@
 // (Algorithm 1) and the Monte Carlo estimators (Monte Carlo section, Eq. stdM).
 #include "common.h"
 #include "pauliwht.h"
+#include "philox.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -137,6 +138,20 @@ struct pw_ctx_s {
     uint64_t samples[4] = {0, 0, 0, 0};
     uint64_t sampled_families[4] = {0, 0, 0, 0};
     LaunchTimer timer{};
+    // learned proposal (library-owned device buffers)
+    struct Made {
+        bool ready = false;
+        MadeDims D{};
+        int t = 0;
+        int maxB = 0;
+        void* block = nullptr;
+        float *P = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+        float *H1 = nullptr, *H2 = nullptr, *O = nullptr, *dO = nullptr, *G1 = nullptr, *G2 = nullptr;
+        double* logq = nullptr;
+        uint64_t* xs = nullptr;
+        float* w = nullptr;
+        int* perm = nullptr;
+    } made;
 };
 
 namespace {
@@ -315,6 +330,7 @@ pw_status pw_ctx_destroy(pw_ctx c) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->made.block) (void)hipFree(c->made.block);
     if (c->ws && c->ws_owned) {
         if (hipStreamSynchronize(c->stream) != hipSuccess || hipFree(c->ws) != hipSuccess)
             s = fail(PW_ERR_HIP, "releasing the library-owned workspace failed");
@@ -604,6 +620,350 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
     r.P = NAN;
     r.nullity = NAN;
     r.nu_cnt = 0;
+    r.n_samples = drawn + 1;
+    r.gap = gap;
+    *out = r;
+    return PW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned proposal
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int MADE_MAXB = 4096;
+
+pw_status made_check(pw_ctx c) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (!c->made.ready) return fail(PW_ERR_NO_STATE, "no learned proposal: call pw_made_init first");
+    return PW_OK;
+}
+
+// Upload up to MADE_MAXB x values (and weights) to the MADE staging buffers.
+pw_status made_stage(pw_ctx c, const uint64_t* xs, const double* w, int64_t count) {
+    auto& M = c->made;
+    PW_HIP(hipMemcpyAsync(M.xs, xs, (size_t)count * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    if (w) {
+        std::vector<float> wf((size_t)count);
+        for (int64_t i = 0; i < count; ++i) wf[i] = (float)w[i];
+        PW_HIP(hipMemcpyAsync(M.w, wf.data(), (size_t)count * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        PW_HIP(hipStreamSynchronize(c->stream));
+    }
+    return PW_OK;
+}
+
+uint64_t splitmix_next(uint64_t& s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+pw_status made_logq_host(pw_ctx c, const uint64_t* xs, int64_t count, double* logq) {
+    auto& M = c->made;
+    for (int64_t i = 0; i < count; i += M.maxB) {
+        const int nb = (int)((count - i) < M.maxB ? (count - i) : M.maxB);
+        pw_status s = made_stage(c, xs + i, nullptr, nb);
+        if (s != PW_OK) return s;
+        PW_HIP(made_forward(M.D, M.P, M.xs, nullptr, nb, nullptr, nullptr, nullptr, M.logq, c->stream));
+        PW_HIP(hipMemcpyAsync(logq + i, M.logq, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        PW_HIP(hipStreamSynchronize(c->stream));
+    }
+    return PW_OK;
+}
+
+}  // namespace
+
+pw_status pw_made_param_count(int n, int hidden, size_t* count) {
+    if (!count) return fail(PW_ERR_ARG, "null output");
+    if (n < 2 || n > 32) return fail(PW_ERR_RANGE, "n=%d outside [2, 32]", n);
+    if (hidden != 64 && hidden != 128 && hidden != 256) return fail(PW_ERR_UNSUPPORTED, "hidden must be 64, 128 or 256");
+    *count = made_dims(n, hidden).total;
+    return PW_OK;
+}
+
+pw_status pw_made_init(pw_ctx c, int n, int hidden, const double* params) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    size_t count = 0;
+    s = pw_made_param_count(n, hidden, &count);
+    if (s != PW_OK) return s;
+    if (!params) return fail(PW_ERR_ARG, "null parameters");
+    auto& M = c->made;
+    if (M.block) {
+        PW_HIP(hipStreamSynchronize(c->stream));
+        PW_HIP(hipFree(M.block));
+        M.block = nullptr;
+    }
+    M.ready = false;
+    M.D = made_dims(n, hidden);
+    M.maxB = MADE_MAXB;
+    const size_t act = (size_t)M.maxB * hidden * sizeof(float);
+    const size_t outb = (size_t)M.maxB * n * sizeof(float);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    const size_t oP = carve(count * 4), og = carve(count * 4), om = carve(count * 4), ov = carve(count * 4);
+    const size_t oH1 = carve(act), oH2 = carve(act), oG1 = carve(act), oG2 = carve(act);
+    const size_t oO = carve(outb), odO = carve(outb);
+    const size_t olq = carve((size_t)M.maxB * 8), oxs = carve((size_t)M.maxB * 8), ow = carve((size_t)M.maxB * 4),
+                 operm = carve((size_t)M.maxB * 4);
+    if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+    PW_HIP(hipMalloc(&M.block, off));
+    char* b = (char*)M.block;
+    M.P = (float*)(b + oP);
+    M.g = (float*)(b + og);
+    M.m = (float*)(b + om);
+    M.v = (float*)(b + ov);
+    M.H1 = (float*)(b + oH1);
+    M.H2 = (float*)(b + oH2);
+    M.G1 = (float*)(b + oG1);
+    M.G2 = (float*)(b + oG2);
+    M.O = (float*)(b + oO);
+    M.dO = (float*)(b + odO);
+    M.logq = (double*)(b + olq);
+    M.xs = (uint64_t*)(b + oxs);
+    M.w = (float*)(b + ow);
+    M.perm = (int*)(b + operm);
+    std::vector<float> pf(count);
+    for (size_t i = 0; i < count; ++i) pf[i] = (float)params[i];
+    PW_HIP(hipMemcpyAsync(M.P, pf.data(), count * 4, hipMemcpyHostToDevice, c->stream));
+    PW_HIP(hipMemsetAsync(M.m, 0, count * 4, c->stream));
+    PW_HIP(hipMemsetAsync(M.v, 0, count * 4, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    M.t = 0;
+    M.ready = true;
+    return PW_OK;
+}
+
+pw_status pw_made_get(pw_ctx c, double* params) {
+    pw_status s = made_check(c);
+    if (s != PW_OK) return s;
+    if (!params) return fail(PW_ERR_ARG, "null output");
+    std::vector<float> pf(c->made.D.total);
+    PW_HIP(hipMemcpyAsync(pf.data(), c->made.P, pf.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < pf.size(); ++i) params[i] = pf[i];
+    return PW_OK;
+}
+
+pw_status pw_made_logq(pw_ctx c, const uint64_t* xs, int64_t count, double* logq) {
+    pw_status s = made_check(c);
+    if (s != PW_OK) return s;
+    if (count < 0 || (count > 0 && (!xs || !logq))) return fail(PW_ERR_ARG, "bad arrays");
+    for (int64_t i = 0; i < count; ++i)
+        if (xs[i] >> c->made.D.n) return fail(PW_ERR_RANGE, "xs[%lld] has bits above n", (long long)i);
+    return made_logq_host(c, xs, count, logq);
+}
+
+pw_status pw_made_grad(pw_ctx c, const uint64_t* xs, const double* w, int64_t count, double* loss, double* grad) {
+    pw_status s = made_check(c);
+    if (s != PW_OK) return s;
+    auto& M = c->made;
+    if (count < 1 || count > M.maxB) return fail(PW_ERR_RANGE, "count must be in [1, %d]", M.maxB);
+    if (!xs || !w || !grad) return fail(PW_ERR_ARG, "null array");
+    double W = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        if (xs[i] >> M.D.n) return fail(PW_ERR_RANGE, "xs[%lld] has bits above n", (long long)i);
+        if (!(w[i] >= 0.0)) return fail(PW_ERR_ARG, "weights must be >= 0");
+        W += w[i];
+    }
+    if (!(W > 0.0)) return fail(PW_ERR_ARG, "weights sum to 0");
+    s = made_stage(c, xs, w, count);
+    if (s != PW_OK) return s;
+    const int nb = (int)count;
+    PW_HIP(made_forward(M.D, M.P, M.xs, nullptr, nb, M.H1, M.H2, M.O, M.logq, c->stream));
+    PW_HIP(made_backward(M.D, M.P, M.xs, nullptr, M.w, (float)(1.0 / W), nb, M.H1, M.H2, M.O, M.dO, M.G1, M.G2,
+                         c->stream));
+    PW_HIP(made_wgrad(M.D, M.xs, nullptr, nb, M.dO, M.G1, M.G2, M.H1, M.H2, M.g, c->stream));
+    std::vector<float> gf(M.D.total);
+    std::vector<double> lq((size_t)count);
+    PW_HIP(hipMemcpyAsync(gf.data(), M.g, gf.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipMemcpyAsync(lq.data(), M.logq, lq.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < gf.size(); ++i) grad[i] = gf[i];
+    if (loss) {
+        double l = 0.0;
+        for (int64_t i = 0; i < count; ++i) l -= w[i] * lq[i];
+        *loss = l / W;
+    }
+    return PW_OK;
+}
+
+pw_status pw_made_train(pw_ctx c, const uint64_t* xs, const double* w, int64_t count, int epochs, int minibatch,
+                        double lr, uint64_t seed, double* final_loss) {
+    pw_status s = made_check(c);
+    if (s != PW_OK) return s;
+    auto& M = c->made;
+    if (count < 1) return fail(PW_ERR_ARG, "no training samples");
+    if (minibatch < 1 || minibatch > M.maxB) return fail(PW_ERR_RANGE, "minibatch must be in [1, %d]", M.maxB);
+    if (epochs < 0 || !(lr > 0.0)) return fail(PW_ERR_ARG, "bad epochs or learning rate");
+    if (!xs || !w) return fail(PW_ERR_ARG, "null array");
+    for (int64_t i = 0; i < count; ++i) {
+        if (xs[i] >> M.D.n) return fail(PW_ERR_RANGE, "xs[%lld] has bits above n", (long long)i);
+        if (!(w[i] >= 0.0)) return fail(PW_ERR_ARG, "weights must be >= 0");
+    }
+    std::vector<int64_t> order((size_t)count);
+    std::vector<uint64_t> bx((size_t)minibatch);
+    std::vector<double> bw((size_t)minibatch);
+    for (int e = 0; e < epochs; ++e) {
+        for (int64_t i = 0; i < count; ++i) order[i] = i;
+        uint64_t st = seed ^ (0xA0761D6478BD642Full * (uint64_t)(e + 1));
+        for (int64_t i = count - 1; i > 0; --i) {      // Fisher-Yates with SplitMix64
+            const int64_t j = (int64_t)(splitmix_next(st) % (uint64_t)(i + 1));
+            const int64_t t = order[i];
+            order[i] = order[j];
+            order[j] = t;
+        }
+        for (int64_t b0 = 0; b0 < count; b0 += minibatch) {
+            const int nb = (int)((count - b0) < minibatch ? (count - b0) : minibatch);
+            double W = 0.0;
+            for (int i = 0; i < nb; ++i) {
+                bx[i] = xs[order[b0 + i]];
+                bw[i] = w[order[b0 + i]];
+                W += bw[i];
+            }
+            if (!(W > 0.0)) continue;
+            s = made_stage(c, bx.data(), bw.data(), nb);
+            if (s != PW_OK) return s;
+            PW_HIP(made_forward(M.D, M.P, M.xs, nullptr, nb, M.H1, M.H2, M.O, nullptr, c->stream));
+            PW_HIP(made_backward(M.D, M.P, M.xs, nullptr, M.w, (float)(1.0 / W), nb, M.H1, M.H2, M.O, M.dO, M.G1,
+                                 M.G2, c->stream));
+            PW_HIP(made_wgrad(M.D, M.xs, nullptr, nb, M.dO, M.G1, M.G2, M.H1, M.H2, M.g, c->stream));
+            ++M.t;
+            PW_HIP(made_adam(M.P, M.g, M.m, M.v, M.D.total, (float)lr, 0.9f, 0.999f, 1e-8f, M.t, c->stream));
+        }
+    }
+    PW_HIP(hipStreamSynchronize(c->stream));
+    if (final_loss) {
+        std::vector<double> lq((size_t)count);
+        s = made_logq_host(c, xs, count, lq.data());
+        if (s != PW_OK) return s;
+        double l = 0.0, W = 0.0;
+        for (int64_t i = 0; i < count; ++i) {
+            l -= w[i] * lq[i];
+            W += w[i];
+        }
+        *final_loss = l / W;
+    }
+    return PW_OK;
+}
+
+pw_status pw_made_sample(pw_ctx c, uint64_t seed, uint64_t offset, int64_t count, uint64_t* xs_out) {
+    pw_status s = made_check(c);
+    if (s != PW_OK) return s;
+    if (count < 0 || (count > 0 && !xs_out)) return fail(PW_ERR_ARG, "bad output");
+    auto& M = c->made;
+    for (int64_t i = 0; i < count; i += M.maxB) {
+        const int64_t nb = (count - i) < M.maxB ? (count - i) : M.maxB;
+        PW_HIP(made_sample(M.D, M.P, seed, offset + (uint64_t)i, nb, M.xs, c->stream));
+        PW_HIP(hipMemcpyAsync(xs_out + i, M.xs, (size_t)nb * 8, hipMemcpyDeviceToHost, c->stream));
+        PW_HIP(hipStreamSynchronize(c->stream));
+    }
+    return PW_OK;
+}
+
+pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, double target_se, uint64_t seed,
+                        double lambda, int64_t pilot, int epochs, int minibatch, double lr, pw_result* out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    s = made_check(c);
+    if (s != PW_OK) return s;
+    if (!out) return fail(PW_ERR_ARG, "null output");
+    if (c->made.D.n != c->n) return fail(PW_ERR_ARG, "learned proposal has n=%d, state has n=%d", c->made.D.n, c->n);
+    if (!(lambda > 0.0 && lambda <= 1.0)) return fail(PW_ERR_ARG, "lambda must be in (0, 1]");
+    if (batch < 1 || batch > c->made.maxB) return fail(PW_ERR_ARG, "batch must be in [1, %d]", c->made.maxB);
+    if (pilot < 1 || max_samples < 3) return fail(PW_ERR_ARG, "need pilot >= 1 and max_samples >= 3");
+    const int n = c->n;
+    const double d = ldexp(1.0, n);
+    (void)d;
+    FamilyRes r0;
+    const uint64_t zero = 0;
+    s = eval_host(c, &zero, 1, eps, &r0);
+    if (s != PW_OK) return s;
+    const double p0 = r0.p;
+    if (!(p0 < 1.0 - 1e-12)) return fail(PW_ERR_UNSUPPORTED, "p(0) = %.17g: no mass on x != 0", p0);
+    // pilot: x ~ p(. | x != 0), training targets t(x) ~ m_2(x), i.e. weights m_2(x) / p(x)
+    std::vector<uint64_t> px((size_t)pilot);
+    std::vector<FamilyRes> pr((size_t)pilot);
+    s = pw_sample_x(c, PW_SAMPLER_MARGINAL_NZ, seed, 0, pilot, px.data());
+    if (s != PW_OK) return s;
+    for (int64_t i = 0; i < pilot; ++i)
+        if (px[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
+    s = eval_host(c, px.data(), pilot, eps, pr.data());
+    if (s != PW_OK) return s;
+    std::vector<double> pw_((size_t)pilot);
+    for (int64_t i = 0; i < pilot; ++i) pw_[i] = pr[i].m[0] / pr[i].p;
+    s = pw_made_train(c, px.data(), pw_.data(), pilot, epochs, minibatch, lr, seed ^ 0x5EEDull, nullptr);
+    if (s != PW_OK) return s;
+    double lq0 = 0.0;
+    s = made_logq_host(c, &zero, 1, &lq0);
+    if (s != PW_OK) return s;
+    const double q0 = exp(lq0);
+    // defensive mixture q = lambda p(.|x!=0) + (1 - lambda) q_theta(.|x!=0), exact weights m / q
+    Running run[4];
+    double gap = r0.gap;
+    uint64_t drawn = 0;
+    const uint64_t draws_max = max_samples - 1;
+    std::vector<uint64_t> xm, xl, xs;
+    std::vector<FamilyRes> res;
+    std::vector<double> lq;
+    int batches = 0;
+    const uint64_t seed_mc = seed + 0x9E3779B97F4A7C15ull;
+    while (drawn < draws_max) {
+        const int64_t nb = (int64_t)((draws_max - drawn) < (uint64_t)batch ? (draws_max - drawn) : (uint64_t)batch);
+        xm.resize((size_t)nb);
+        xl.resize((size_t)nb);
+        xs.resize((size_t)nb);
+        res.resize((size_t)nb);
+        lq.resize((size_t)nb);
+        s = pw_sample_x(c, PW_SAMPLER_MARGINAL_NZ, seed_mc, drawn, nb, xm.data());
+        if (s != PW_OK) return s;
+        s = pw_made_sample(c, seed_mc, drawn, nb, xl.data());
+        if (s != PW_OK) return s;
+        for (int64_t i = 0; i < nb; ++i) {
+            uint64_t W0, W1;
+            philox_words(seed_mc, drawn + (uint64_t)i, 0u, STREAM_MIX, W0, W1);
+            const double u = (double)(W0 >> 11) * 0x1.0p-53;
+            xs[i] = u < lambda ? xm[i] : xl[i];
+            if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "a sampler could not draw x != 0 in 64 attempts");
+        }
+        s = eval_host(c, xs.data(), nb, eps, res.data());
+        if (s != PW_OK) return s;
+        s = made_logq_host(c, xs.data(), nb, lq.data());
+        if (s != PW_OK) return s;
+        for (int64_t i = 0; i < nb; ++i) {
+            const FamilyRes& f = res[i];
+            const double q = lambda * f.p / (1.0 - p0) + (1.0 - lambda) * exp(lq[i]) / (1.0 - q0);
+            const double wgt = 1.0 / q;
+            for (int a = 0; a < 3; ++a) run[a].add(wgt * f.m[a]);
+            run[3].add(wgt * f.ent);
+            gap = fmax(gap, f.gap);
+        }
+        drawn += (uint64_t)nb;
+        ++batches;
+        const double S2 = r0.m[0] + run[0].mean;
+        const double Mse = sqrt(run[0].var() / run[0].n) / (log(2.0) * S2);
+        if (batches >= 2 && target_se > 0 && Mse <= target_se) break;
+    }
+    pw_result r;
+    memset(&r, 0, sizeof r);
+    for (int a = 0; a < 3; ++a) {
+        const double S = r0.m[a] + run[a].mean;
+        const double se = sqrt(run[a].var() / run[a].n);
+        r.S[a] = S;
+        r.S_se[a] = se;
+        r.M[a] = log2(S) / (1.0 - (a + 2)) - n;
+        r.M_se[a] = se / (fabs(1.0 - (a + 2)) * log(2.0) * S);
+        r.r[a] = sqrt(run[a].var()) / S;
+    }
+    r.L = r0.ent + run[3].mean;
+    r.L_se = sqrt(run[3].var() / run[3].n);
+    r.M1 = -r.L / ldexp(1.0, n);
+    r.M1_se = r.L_se / ldexp(1.0, n);
+    r.P = NAN;
+    r.nullity = NAN;
     r.n_samples = drawn + 1;
     r.gap = gap;
     *out = r;

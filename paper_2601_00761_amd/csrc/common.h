@@ -97,4 +97,22 @@ size_t cdf_blk_elems(int n);
 hipError_t sample_marginal(int n, const double* d_cdf, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs,
                            hipStream_t st);
 
+// Learned proposal (masked autoregressive network over the bits of x).
+struct MadeDims {
+    int n, h;
+    size_t oW1, ob1, oW2, ob2, oW3, ob3, oA, total;
+};
+MadeDims made_dims(int n, int h);
+hipError_t made_forward(const MadeDims& D, const float* P, const uint64_t* xs, const int* perm, int B, float* H1,
+                        float* H2, float* O, double* logq, hipStream_t st);
+hipError_t made_backward(const MadeDims& D, const float* P, const uint64_t* xs, const int* perm, const float* w,
+                         float invW, int B, const float* H1, const float* H2, const float* O, float* dO, float* G1,
+                         float* G2, hipStream_t st);
+hipError_t made_wgrad(const MadeDims& D, const uint64_t* xs, const int* perm, int B, const float* dO, const float* G1,
+                      const float* G2, const float* H1, const float* H2, float* grad, hipStream_t st);
+hipError_t made_adam(float* P, const float* g, float* m, float* v, size_t count, float lr, float b1, float b2,
+                     float eps, int t, hipStream_t st);
+hipError_t made_sample(const MadeDims& D, const float* P, uint64_t seed, uint64_t offset, int64_t count, uint64_t* xs,
+                       hipStream_t st);
+
 }  // namespace pw

@@ -9,36 +9,17 @@
 // counter (i_lo, i_hi, attempt, stream) and key (seed_lo, seed_hi), so the
 // list of sample i is reproducible and independent of batching.
 #include "common.h"
+#include "philox.h"
 
 namespace pw {
 namespace {
 
-constexpr uint32_t STREAM_UNIFORM = 0x554E4946u;   // "UNIF"
-constexpr uint32_t STREAM_MARGINAL = 0x4D415247u;  // "MARG"
 constexpr int MAX_ATTEMPTS = 64;
 constexpr int CDF_CHUNK = 4096;                      // amplitudes per scan workgroup
 
-__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
 __device__ __forceinline__ void words(uint64_t seed, uint64_t g, uint32_t attempt, uint32_t stream, uint64_t& W0,
                                       uint64_t& W1) {
-    uint32_t c[4] = {(uint32_t)g, (uint32_t)(g >> 32), attempt, stream};
-    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    W0 = ((uint64_t)c[1] << 32) | c[0];
-    W1 = ((uint64_t)c[3] << 32) | c[2];
+    philox_words(seed, g, attempt, stream, W0, W1);
 }
 
 __global__ void k_uniform(int n, uint64_t seed, uint64_t offset, int64_t count, uint64_t* __restrict__ xs) {

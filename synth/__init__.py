@@ -21,6 +21,7 @@ from .states import (haar_state, psi_m_state, product_state, stabilizer_product_
 from .clifford import clifford2_table, CLIFFORD2_ORDER
 from .circuits import (Gate, brickwall_pairs, random_brickwall_clifford, tdoped_stream,
                        gates_to_arrays, t_gate, GATE_2Q, GATE_1Q_DIAG)
+from .made_init import made_init, made_sizes, made_param_count
 
 __all__ = [
     "splitmix64", "uniforms", "normals", "stream_seed",
@@ -29,6 +30,7 @@ __all__ = [
     "clifford2_table", "CLIFFORD2_ORDER",
     "Gate", "brickwall_pairs", "random_brickwall_clifford", "tdoped_stream",
     "gates_to_arrays", "t_gate", "GATE_2Q", "GATE_1Q_DIAG",
+    "made_init", "made_sizes", "made_param_count",
     "SEED_BASE",
 ]
 
