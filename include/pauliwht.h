@@ -222,6 +222,23 @@ PW_API pw_status pw_mc_learned(pw_ctx ctx, double eps, int batch, uint64_t max_s
                                uint64_t seed, double lambda, int64_t pilot, int epochs, int minibatch, double lr,
                                pw_result* out);
 
+/* Stabilizer Renyi entropy of the reduced state rho_A on the first n_a qubits
+ * (Supplemental Material, mixed states, Eq. Msre-mixed):
+ *   M_alpha(rho_A) = log2(W_alpha)/(1 - alpha) - n_a - S_2(rho_A),
+ *   W_alpha = sum_{P on A} |Tr(rho_A P)|^{2 alpha} / d_A^alpha,  S_2 = -log2 Tr rho_A^2.
+ * rho_A = Psi Psi^dagger (Psi[a, e] = psi(a + 2^{n_a} e)) is formed on the device,
+ * then every x_A family is the n_a-bit WHT of h(a) = rho_A[a ^ x_A, a].  1 <= n_a <=
+ * min(n, 14 (c64) / 13 (c128)); rho_A (d_A^2 amplitudes) is library-owned. */
+typedef struct {
+    double W[3];        /* W_alpha, alpha = 2, 3, 4 (NaN above pw_set_moments)     */
+    double purity;      /* Tr rho_A^2 = sum_{P on A} |c_P|^2 / d_A                 */
+    double S2;          /* -log2 purity                                              */
+    double M[3];        /* M_alpha(rho_A)                                            */
+    double L;           /* sum_{P on A} c_P^2 log2 c_P^2                             */
+    uint64_t families;  /* 2^{n_a}                                                   */
+} pw_mixed_result;
+PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out);
+
 /* Highest moment order computed per family: 4 (default: alpha = 2, 3, 4) or 2
  * (alpha = 2 only; m[1], m[2], S[1], S[2], M[1], M[2] are then NaN).  M_1, p(x)
  * and the nullity count are always computed. */

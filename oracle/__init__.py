@@ -55,6 +55,7 @@ def lib():
         L.pwo_sample_marginal_nz.argtypes = [ctypes.c_int, _dp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                              _u64p, _dp]
         L.pwo_sample_marginal_nz.restype = ctypes.c_int64
+        L.pwo_mixed.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp]
         _LIB = L
     return _LIB
 
@@ -203,6 +204,22 @@ def sample_marginal_nz(psi, seed, offset, count, return_cdf=False):
     if return_cdf:
         return xs, failed, C
     return xs, failed
+
+
+def mixed(psi, n_a):
+    """Partial-FWHT sums for the reduced state on qubits 0..n_a-1:
+    W_alpha = sum_{P on A} |c_P|^{2 alpha}/d_A^alpha (alpha = 2, 3, 4), purity Tr rho_A^2,
+    and M_alpha(rho_A) = log2(W_alpha)/(1 - alpha) - n_a - S_2, S_2 = -log2(purity)
+    (Eq. Msre-mixed)."""
+    a, p = _c128(psi)
+    n = _nq(a)
+    W = np.empty(3)
+    pur = ctypes.c_double()
+    L = ctypes.c_double()
+    _chk(lib().pwo_mixed(n, p, int(n_a), W.ctypes.data_as(_dp), ctypes.byref(pur), ctypes.byref(L)))
+    S2 = -math.log2(pur.value)
+    M = {al: math.log2(W[al - 2]) / (1.0 - al) - n_a - S2 for al in (2, 3, 4)}
+    return dict(W=W, purity=pur.value, S2=S2, M=M, L=L.value)
 
 
 # ---------------------------------------------------------------------------

@@ -447,3 +447,45 @@ PWO_EXPORT int64_t pwo_sample_marginal_nz(int n, const double* psi_in, uint64_t 
     if (!C_out) free(C);
     return failed;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Mixed-state SRE of the reduced state on the first n_a qubits (Supplemental */
+/* Material, mixed states, Eq. Msre-mixed): for every x_A,                    */
+/*   h(a) = sum_e conj(psi(a, e)) psi(a ^ x_A, e),  b = a + 2^{n_a} e,        */
+/* then an n_a-bit FWHT over a gives every c_P with P supported on A.         */
+/* Outputs W[alpha-2] = sum_P |c_P|^{2 alpha} / d_A^alpha (alpha = 2..4),     */
+/* *purity = sum_P |c_P|^2 / d_A = Tr rho_A^2, *L = sum_P c^2 log2 c^2.       */
+/* ------------------------------------------------------------------------ */
+PWO_EXPORT int pwo_mixed(int n, const double* psi_in, int n_a, double* W, double* purity, double* L) {
+    if (n < 1 || n > 30 || n_a < 1 || n_a > n || n_a > 16 || !psi_in || !W || !purity || !L) return -1;
+    const cplx* psi = (const cplx*)psi_in;
+    const uint64_t dA = 1ull << n_a, dE = 1ull << (n - n_a);
+    nsum sw[3], sp = {0, 0}, sl = {0, 0};
+    memset(sw, 0, sizeof sw);
+    cplx* h = (cplx*)malloc(sizeof(cplx) * dA);
+    if (!h) return -2;
+    for (uint64_t xa = 0; xa < dA; ++xa) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t a = 0; a < (int64_t)dA; ++a) {
+            double sr = 0.0, si = 0.0;
+            for (uint64_t e = 0; e < dE; ++e) {
+                cplx t = cmul(cconj(psi[(uint64_t)a + (e << n_a)]), psi[((uint64_t)a ^ xa) + (e << n_a)]);
+                sr += t.re; si += t.im;
+            }
+            h[a].re = sr; h[a].im = si;
+        }
+        fwht_inplace(h, dA, 0);
+        for (uint64_t z = 0; z < dA; ++z) {
+            double a2 = cabs2(h[z]);
+            nadd(&sp, a2);
+            if (a2 > 0.0) nadd(&sl, a2 * log2(a2));
+            double pw = a2;
+            for (int al = 2; al <= 4; ++al) { pw *= a2; nadd(&sw[al - 2], pw); }
+        }
+    }
+    free(h);
+    for (int al = 2; al <= 4; ++al) W[al - 2] = ldexp(nval(&sw[al - 2]), -n_a * al);
+    *purity = ldexp(nval(&sp), -n_a);
+    *L = nval(&sl);
+    return 0;
+}

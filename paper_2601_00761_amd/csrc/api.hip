@@ -152,6 +152,8 @@ struct pw_ctx_s {
         float* w = nullptr;
         int* perm = nullptr;
     } made;
+    void* rho = nullptr;        // reduced density matrix (library-owned)
+    size_t rho_bytes = 0;
 };
 
 namespace {
@@ -331,6 +333,7 @@ pw_status pw_ctx_destroy(pw_ctx c) {
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->made.block) (void)hipFree(c->made.block);
+    if (c->rho) (void)hipFree(c->rho);
     if (c->ws && c->ws_owned) {
         if (hipStreamSynchronize(c->stream) != hipSuccess || hipFree(c->ws) != hipSuccess)
             s = fail(PW_ERR_HIP, "releasing the library-owned workspace failed");
@@ -966,6 +969,53 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
     r.nullity = NAN;
     r.n_samples = drawn + 1;
     r.gap = gap;
+    *out = r;
+    return PW_OK;
+}
+
+pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (!out) return fail(PW_ERR_ARG, "null output");
+    const bool dbl = c->dtype == PW_C128;
+    const int amax = dbl ? 13 : 14;
+    if (n_a < 1 || n_a > c->n || n_a > amax) return fail(PW_ERR_RANGE, "n_a=%d outside [1, min(n, %d)]", n_a, amax);
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
+    const size_t dA = (size_t)1 << n_a;
+    const size_t bytes = dA * dA * esize(c->dtype);
+    if (c->rho_bytes < bytes) {
+        if (c->rho) {
+            PW_HIP(hipStreamSynchronize(c->stream));
+            PW_HIP(hipFree(c->rho));
+            c->rho = nullptr;
+            c->rho_bytes = 0;
+        }
+        if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+        PW_HIP(hipMalloc(&c->rho, bytes));
+        c->rho_bytes = bytes;
+    }
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    PW_HIP(reduced_density(dbl, c->psi, c->n, n_a, c->rho, c->stream));
+    FamilyRes* fam = at<FamilyRes>(c, c->L.fam);
+    for (size_t x0 = 0; x0 < dA; x0 += MAX_BATCH) {
+        const int nb = (int)((dA - x0) < (size_t)MAX_BATCH ? (dA - x0) : (size_t)MAX_BATCH);
+        PW_HIP(eval_reduced_batch(dbl, c->max_alpha, c->rho, n_a, x0, nb, eps, fam + x0, c->stream));
+    }
+    SweepSums* sw = at<SweepSums>(c, c->L.sweep);
+    PW_HIP(reduce_families(fam, (int64_t)dA, sw, c->stream));
+    SweepSums h;
+    PW_HIP(hipMemcpyAsync(&h, sw, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    pw_mixed_result r;
+    memset(&r, 0, sizeof r);
+    r.purity = h.P;
+    r.S2 = -log2(h.P);
+    for (int a = 0; a < 3; ++a) {
+        r.W[a] = h.S[a];
+        r.M[a] = log2(h.S[a]) / (1.0 - (a + 2)) - n_a - r.S2;
+    }
+    r.L = h.L;
+    r.families = h.count;
     *out = r;
     return PW_OK;
 }

@@ -72,6 +72,12 @@ hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, c
                       int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
                       const LaunchTimer* tm = nullptr);
 
+// Mixed states: rho_A = Psi Psi^dagger of the first na qubits (d_A x d_A, row-major),
+// and the families x_A = x0 .. x0 + nb - 1 of the reduced state (na - 1 <= 13 / 12).
+hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st);
+hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, uint64_t x0, int nb, double eps,
+                              FamilyRes* out, hipStream_t st);
+
 // Fixed-order sum of count per-family results.
 hipError_t reduce_families(const FamilyRes* in, int64_t count, SweepSums* out, hipStream_t st);
 

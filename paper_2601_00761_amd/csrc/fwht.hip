@@ -182,6 +182,38 @@ __device__ __forceinline__ void load_products_hi(const cx<R>* __restrict__ psi, 
     }
 }
 
+// Mixed states (Supplemental Material, mixed states): for Paulis supported on the
+// first n_a qubits the family of x_A is the n_a-bit WHT of
+//     h(a) = sum_e conj(psi(a, e)) psi(a ^ x_A, e) = rho_A[a ^ x_A, a],
+// rho_A = Psi Psi^dagger the reduced density matrix (row-major, d_A x d_A).  h has the
+// same Hermitian symmetry as f_x, so the half-size transform applies unchanged.
+template <typename R, int TL, int RL>
+__device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ rho, int na, uint32_t x, R (&re)[1 << RL],
+                                             R (&im)[1 << RL]) {
+    const uint32_t tid = threadIdx.x;
+    const size_t dA = (size_t)1 << na;
+    if (x != 0u) {
+        const int p = 31 - __builtin_clz(x);
+        const uint32_t lowmask = (1u << p) - 1u;
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) {
+            const uint32_t bp = tid + ((uint32_t)j << TL);
+            const uint32_t b = (bp & lowmask) | ((bp & ~lowmask) << 1);
+            const cx<R> v = rho[(size_t)(b ^ x) * dA + b];
+            re[j] = v.re;
+            im[j] = v.im;
+        }
+    } else {
+        const uint32_t half = (uint32_t)(dA >> 1);
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) {
+            const uint32_t bp = tid + ((uint32_t)j << TL);
+            re[j] = rho[(size_t)bp * dA + bp].re;
+            im[j] = rho[(size_t)(bp + half) * dA + bp + half].re;
+        }
+    }
+}
+
 struct AccD {
     double s1, ent, s2, s3, s4, gap;
     unsigned cnt;
@@ -374,6 +406,85 @@ k_fused(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     tile_fwht<R, TL, RL, 0>(re, im, lds);
     const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
     if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, n);
+}
+
+// Family of x_A for the reduced state (one workgroup per family, n_a - 1 = K).
+template <typename R, int TL, int RL, int MOM>
+__global__ void __launch_bounds__(1 << TL)
+k_fused_reduced(const cx<R>* __restrict__ rho, int na, uint64_t x0, R eps, FamilyRes* __restrict__ out) {
+    constexpr int K = TL + RL;
+    constexpr int NT = 1 << TL;
+    __shared__ cx<R> lds[Lds<K>::elems];
+    __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
+    const uint32_t slot = blockIdx.x;
+    const uint64_t x = x0 + slot;
+    R re[1 << RL], im[1 << RL];
+    load_reduced<R, TL, RL>(rho, na, (uint32_t)x, re, im);
+    tile_fwht<R, TL, RL, 0>(re, im, lds);
+    const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
+    if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, na);
+}
+
+// rho_A[a, a'] = sum_e psi(a + e d_A) conj(psi(a' + e d_A)): 64 x 64 output tiles, e in
+// chunks of 16 staged through LDS, 4 x 4 outputs per thread.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
+    __shared__ cx<R> ta[16][64], tb[16][64];
+    const uint32_t dA = 1u << na;
+    const uint64_t dE = 1ull << ne;
+    const uint32_t r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    R accr[4][4], acci[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = R(0);
+    for (uint64_t e0 = 0; e0 < dE; e0 += 16) {
+        for (int l = threadIdx.x; l < 16 * 64; l += 256) {
+            const int ee = l >> 6, aa = l & 63;
+            const uint64_t e = e0 + ee;
+            cx<R> va, vb;
+            va.re = va.im = vb.re = vb.im = R(0);
+            if (e < dE) {
+                if (r0 + aa < dA) va = psi[(size_t)(r0 + aa) + (e << na)];
+                if (c0 + aa < dA) vb = psi[(size_t)(c0 + aa) + (e << na)];
+            }
+            ta[ee][aa] = va;
+            tb[ee][aa] = vb;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int ee = 0; ee < 16; ++ee) {
+            cx<R> a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = ta[ee][ty * 4 + i];
+                b[i] = tb[ee][tx * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    // a conj(b)
+                    accr[i][j] = fma(a[i].re, b[j].re, fma(a[i].im, b[j].im, accr[i][j]));
+                    acci[i][j] = fma(a[i].im, b[j].re, fma(-a[i].re, b[j].im, acci[i][j]));
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t r = r0 + ty * 4 + i, c = c0 + tx * 4 + j;
+            if (r < dA && c < dA) {
+                cx<R> v;
+                v.re = accr[i][j];
+                v.im = acci[i][j];
+                rho[(size_t)r * dA + c] = v;
+            }
+        }
 }
 
 template <typename R, int TL, int RL>
@@ -653,6 +764,31 @@ hipError_t launch_fused(const void* psi, int n, const uint64_t* xs, uint64_t x0,
     }
 }
 
+template <typename R, int K, int MOM>
+hipError_t launch_reduced_k(const void* rho, int na, uint64_t x0, int nb, R eps, FamilyRes* out, hipStream_t st) {
+    constexpr int RL0 = K < 4 ? K : 4;
+    constexpr int TL = K == 13 ? 9 : K - RL0;
+    constexpr int RL = K - TL;
+    hipLaunchKernelGGL((k_fused_reduced<R, TL, RL, MOM>), dim3(nb), dim3(1 << TL), 0, st, (const cx<R>*)rho, na, x0,
+                       eps, out);
+    return hipGetLastError();
+}
+
+template <typename R, int MOM>
+hipError_t launch_reduced(const void* rho, int na, uint64_t x0, int nb, R eps, FamilyRes* out, hipStream_t st) {
+    switch (na - 1) {
+#define PW_CASE(K) \
+    case K: return launch_reduced_k<R, K, MOM>(rho, na, x0, nb, eps, out, st);
+        PW_CASE(0) PW_CASE(1) PW_CASE(2) PW_CASE(3) PW_CASE(4) PW_CASE(5) PW_CASE(6)
+        PW_CASE(7) PW_CASE(8) PW_CASE(9) PW_CASE(10) PW_CASE(11) PW_CASE(12)
+#undef PW_CASE
+        case 13:
+            if constexpr (sizeof(R) == 4) return launch_reduced_k<R, 13, MOM>(rho, na, x0, nb, eps, out, st);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R, int TL, bool LAST, int MOM>
 hipError_t launch_column_t(int s, dim3 grid, cx<R>* work, int n, int lo, const uint64_t* xs, uint64_t x0, R eps,
                            FamilyRes* parts, hipStream_t st, const LaunchTimer* tm) {
@@ -776,6 +912,27 @@ hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, c
                               : eval_batch_t<double, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm);
     return max_alpha >= 4 ? eval_batch_t<float, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm)
                           : eval_batch_t<float, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm);
+}
+
+hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st) {
+    const unsigned tiles = (unsigned)(((1u << na) + 63) / 64);
+    if (dbl)
+        hipLaunchKernelGGL(k_rho<double>, dim3(tiles, tiles), dim3(256), 0, st, (const cx<double>*)psi, na, n - na,
+                           (cx<double>*)rho);
+    else
+        hipLaunchKernelGGL(k_rho<float>, dim3(tiles, tiles), dim3(256), 0, st, (const cx<float>*)psi, na, n - na,
+                           (cx<float>*)rho);
+    return hipGetLastError();
+}
+
+hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, uint64_t x0, int nb, double eps,
+                              FamilyRes* out, hipStream_t st) {
+    if (nb <= 0) return hipSuccess;
+    if (dbl)
+        return max_alpha >= 4 ? launch_reduced<double, 4>(rho, na, x0, nb, eps, out, st)
+                              : launch_reduced<double, 2>(rho, na, x0, nb, eps, out, st);
+    return max_alpha >= 4 ? launch_reduced<float, 4>(rho, na, x0, nb, (float)eps, out, st)
+                          : launch_reduced<float, 2>(rho, na, x0, nb, (float)eps, out, st);
 }
 
 hipError_t reduce_families(const FamilyRes* in, int64_t count, SweepSums* out, hipStream_t st) {

@@ -298,3 +298,41 @@ def test_haar_n24_ten_samples_worked_example():
     exact = math.log2(2 ** n + 3) - 2
     assert abs(M - exact) < 5 * max(sM, g["uncertainty"])
     assert abs(M - g["value"]) < 0.002
+
+
+# --------------------------------------------------------------------------- mixed states (partial FWHT)
+
+def test_mixed_matches_bruteforce_restriction():
+    # c_P for P supported on the first n_a qubits are the full-state c_P with x, z < 2^{n_a}
+    n = 6
+    psi = synth.haar_state(n, 301)
+    c = oracle.bruteforce(psi)
+    for n_a in (1, 2, 4, 6):
+        dA = 1 << n_a
+        sub = np.abs(c[:dA, :dA]) ** 2
+        r = oracle.mixed(psi, n_a)
+        assert abs(r["purity"] - sub.sum() / dA) < 1e-13
+        for al in (2, 3, 4):
+            assert abs(r["W"][al - 2] - np.sum(sub ** al) / dA ** al) < 1e-14
+        if n_a == n:
+            assert abs(r["S2"]) < 1e-12   # pure: the mixed formula reduces to Eq. SRE-def
+            full = oracle.alg1(psi)
+            assert abs(r["M"][2] - full["M"][2]) < 1e-11
+
+
+def test_mixed_product_and_maximally_entangled():
+    # A in a pure product with B: rho_A pure, M_alpha(rho_A) = M_alpha of the A factor
+    labels = ["x+", "y-", "z+"]
+    phiA = synth.states.stabilizer_product(labels, t_on={0, 1})
+    phiB = synth.haar_state(3, 303)
+    psi = np.kron(phiB, phiA)                 # A = qubits 0..2 (low bits)
+    r = oracle.mixed(psi, 3)
+    assert abs(r["S2"]) < 1e-12
+    assert abs(r["M"][2] - 2 * math.log2(4 / 3)) < 1e-11
+    # Bell pairs between qubit j (A) and j + 3 (B): rho_A = I/8, only P = I survives, M = 0, S_2 = 3
+    n = 6
+    psi = np.zeros(1 << n, dtype=complex)
+    for a in range(8):
+        psi[a + (a << 3)] = 1 / math.sqrt(8)
+    r = oracle.mixed(psi, 3)
+    assert abs(r["S2"] - 3) < 1e-12 and abs(r["M"][2]) < 1e-12
