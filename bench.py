@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--no-mc-leg", action="store_true", help="skip the N=28 Monte Carlo leg")
     ap.add_argument("--mc-eta", type=int, nargs="+", default=[4],
                     help="scrambling ratios of the N=28 Monte Carlo leg (the workload lists 1, 4 and 16)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="families per launch (0: the library default for the state size)")
     ap.add_argument("--max-alpha", type=int, default=2, choices=(2, 4),
                     help="moments computed per family (the workload asks for M_1, M_2 and the nullity)")
     args = ap.parse_args()
@@ -209,6 +211,8 @@ def main():
     def leg(dtype, psi_dev, steps, warmup, eps, timing):
         ctx = pw.Context(0, stream)
         pw.pw_set_moments(ctx.h, args.max_alpha)
+        if args.batch:
+            ctx.reserve(n, dtype, args.batch)
         ctx.bind(psi_dev, dtype)
         for _ in range(warmup):
             ctx.exact(eps)
