@@ -239,6 +239,13 @@ typedef struct {
 } pw_mixed_result;
 PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out);
 
+/* Graph replay for pw_mc: when enabled, one sampling step (device-side draws whose
+ * counters come from a device counter, evaluation of their families, counter
+ * increment) is captured once per pw_mc call as a HIP graph on a private
+ * non-blocking stream and replayed for every full batch of size <= the workspace
+ * batch.  Results are bitwise those of the eager path. */
+PW_API pw_status pw_set_graphs(pw_ctx ctx, int enable);
+
 /* Highest moment order computed per family: 4 (default: alpha = 2, 3, 4) or 2
  * (alpha = 2 only; m[1], m[2], S[1], S[2], M[1], M[2] are then NaN).  M_1, p(x)
  * and the nullity count are always computed. */

@@ -20,7 +20,7 @@ __all__ = [
     "PWError", "PW_C128", "PW_C64", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
@@ -108,6 +108,7 @@ def _load():
         "pw_exact": ([_vp, _dbl, ctypes.POINTER(pw_result)], _int),
         "pw_mc": ([_vp, _int, _dbl, _int, _u64, _dbl, _u64, ctypes.POINTER(pw_result)], _int),
         "pw_set_moments": ([_vp, _int], _int),
+        "pw_set_graphs": ([_vp, _int], _int),
         "pw_mixed": ([_vp, _int, _dbl, ctypes.POINTER(pw_mixed_result)], _int),
         "pw_made_param_count": ([_int, _int, ctypes.POINTER(ctypes.c_size_t)], _int),
         "pw_made_init": ([_vp, _int, _int, _vp], _int),
@@ -245,6 +246,10 @@ def pw_mc(ctx, sampler, eps, batch, max_samples, target_se, seed):
 
 def pw_set_moments(ctx, max_alpha):
     _check(_L.pw_set_moments(ctx, int(max_alpha)))
+
+
+def pw_set_graphs(ctx, enable):
+    _check(_L.pw_set_graphs(ctx, int(bool(enable))))
 
 
 def pw_mixed(ctx, n_a, eps):

@@ -56,7 +56,7 @@ size_t esize(pw_dtype dt) { return dt == PW_C128 ? 16 : 8; }
 
 // Workspace layout for (n, dtype, batch).
 struct Layout {
-    size_t work, parts, xs, xres, fam, sweep, cdf, cdfblk, norm, total;
+    size_t work, parts, xs, xres, fam, sweep, cdf, cdfblk, norm, ctr, total;
 };
 
 Layout layout_for(int n, pw_dtype dt, int batch) {
@@ -89,6 +89,8 @@ Layout layout_for(int n, pw_dtype dt, int batch) {
     off += align256(cdf_blk_elems(n) * sizeof(double));
     L.norm = off;
     off += align256((size_t)(norm2_parts(n) + 2) * sizeof(double));
+    L.ctr = off;
+    off += 256;
     L.total = off;
     return L;
 }
@@ -154,6 +156,11 @@ struct pw_ctx_s {
     } made;
     void* rho = nullptr;        // reduced density matrix (library-owned)
     size_t rho_bytes = 0;
+    // graph replay of Monte Carlo sampling steps
+    bool use_graphs = false;
+    hipStream_t gstream = nullptr;  // non-blocking capture stream (default priority)
+    hipEvent_t gfork = nullptr, gjoin = nullptr;
+    bool capturing = false;
 };
 
 namespace {
@@ -189,7 +196,7 @@ void timer_commit(void* self, int k, int families, hipEvent_t a, hipEvent_t b) {
     c->pending.push_back({a, b, k, families});
 }
 
-const LaunchTimer* timer_of(pw_ctx c) { return c->timing_every > 0 ? &c->timer : nullptr; }
+const LaunchTimer* timer_of(pw_ctx c) { return (c->timing_every > 0 && !c->capturing) ? &c->timer : nullptr; }
 
 pw_status check_ctx(pw_ctx c) {
     if (!c) return fail(PW_ERR_ARG, "null context");
@@ -300,6 +307,51 @@ struct Running {
     double var() const { return n > 1 ? m2 / (n - 1) : NAN; }
 };
 
+// Graph replay of one Monte Carlo step: draw `nb` x on the device (counters start at
+// the device counter), evaluate their families into the per-family buffer, advance the
+// counter.  The step is captured once on a private non-blocking stream and replayed;
+// it records no memset or copy nodes.
+struct McGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~McGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+pw_status mc_step_enqueue(pw_ctx c, pw_sampler sampler, uint64_t seed, int nb, double eps, hipStream_t st) {
+    uint64_t* dx = at<uint64_t>(c, c->L.xs);
+    uint64_t* dctr = at<uint64_t>(c, c->L.ctr);
+    if (sampler == PW_SAMPLER_UNIFORM_NZ) PW_HIP(sample_uniform(c->n, seed, 0, nb, dx, st, dctr));
+    else PW_HIP(sample_marginal(c->n, at<double>(c, c->L.cdf), seed, 0, nb, dx, st, dctr));
+    PW_HIP(eval_batch(c->P, c->dtype == PW_C128, c->max_alpha, c->psi, dx, 0, nb, eps, c->ws + c->L.work,
+                      at<FamilyRes>(c, c->L.parts), at<FamilyRes>(c, c->L.xres), st, nullptr));
+    PW_HIP(bump_counter(dctr, (uint64_t)nb, st));
+    return PW_OK;
+}
+
+pw_status mc_graph_build(pw_ctx c, pw_sampler sampler, uint64_t seed, int nb, double eps, McGraph& g) {
+    if (!c->gstream) {
+        PW_HIP(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        PW_HIP(hipEventCreateWithFlags(&c->gfork, hipEventDisableTiming));
+        PW_HIP(hipEventCreateWithFlags(&c->gjoin, hipEventDisableTiming));
+    }
+    c->capturing = true;
+    hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        c->capturing = false;
+        return fail(PW_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    pw_status s = mc_step_enqueue(c, sampler, seed, nb, eps, c->gstream);
+    e = hipStreamEndCapture(c->gstream, &g.graph);
+    c->capturing = false;
+    if (s != PW_OK) return s;
+    if (e != hipSuccess) return fail(PW_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    PW_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    return PW_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -334,6 +386,12 @@ pw_status pw_ctx_destroy(pw_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->made.block) (void)hipFree(c->made.block);
     if (c->rho) (void)hipFree(c->rho);
+    if (c->gstream) {
+        (void)hipStreamSynchronize(c->gstream);
+        (void)hipStreamDestroy(c->gstream);
+    }
+    if (c->gfork) (void)hipEventDestroy(c->gfork);
+    if (c->gjoin) (void)hipEventDestroy(c->gjoin);
     if (c->ws && c->ws_owned) {
         if (hipStreamSynchronize(c->stream) != hipSuccess || hipFree(c->ws) != hipSuccess)
             s = fail(PW_ERR_HIP, "releasing the library-owned workspace failed");
@@ -581,17 +639,42 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
     std::vector<FamilyRes> res;
     const uint64_t draws_max = max_samples - 1;
     int batches = 0;
+    const bool graphs = c->use_graphs && batch <= c->batch;
+    McGraph g;
+    if (graphs) {
+        if (sampler == PW_SAMPLER_MARGINAL_NZ && !c->cdf_valid) {
+            PW_HIP(build_cdf(c->dtype == PW_C128, c->psi, c->n, at<double>(c, c->L.cdf), at<double>(c, c->L.cdfblk),
+                             c->stream));
+            c->cdf_valid = true;
+        }
+        s = mc_graph_build(c, sampler, seed, batch, eps, g);
+        if (s != PW_OK) return s;
+        const uint64_t zero64 = 0;
+        PW_HIP(hipMemcpyAsync(at<uint64_t>(c, c->L.ctr), &zero64, sizeof zero64, hipMemcpyHostToDevice, c->stream));
+        PW_HIP(hipEventRecord(c->gfork, c->stream));
+        PW_HIP(hipStreamWaitEvent(c->gstream, c->gfork, 0));
+    }
     while (drawn < draws_max) {
         const int64_t nb = (int64_t)((draws_max - drawn) < (uint64_t)batch ? (draws_max - drawn) : (uint64_t)batch);
         xs.resize((size_t)nb);
         res.resize((size_t)nb);
-        s = pw_sample_x(c, sampler, seed, drawn, nb, xs.data());
-        if (s != PW_OK) return s;
-        for (int64_t i = 0; i < nb; ++i)
-            if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
-        s = eval_host(c, xs.data(), nb, eps, res.data());
-        if (s != PW_OK) return s;
+        if (graphs && nb == batch) {
+            PW_HIP(hipGraphLaunch(g.exec, c->gstream));
+            PW_HIP(hipMemcpyAsync(res.data(), at<FamilyRes>(c, c->L.xres), (size_t)nb * sizeof(FamilyRes),
+                                  hipMemcpyDeviceToHost, c->gstream));
+            PW_HIP(hipStreamSynchronize(c->gstream));
+            for (int64_t i = 0; i < nb; ++i) xs[i] = res[i].x;
+        } else {
+            if (graphs) PW_HIP(hipStreamSynchronize(c->gstream));
+            s = pw_sample_x(c, sampler, seed, drawn, nb, xs.data());
+            if (s != PW_OK) return s;
+            for (int64_t i = 0; i < nb; ++i)
+                if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
+            s = eval_host(c, xs.data(), nb, eps, res.data());
+            if (s != PW_OK) return s;
+        }
         for (int64_t i = 0; i < nb; ++i) {
+            if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
             const FamilyRes& f = res[i];
             const double w = sampler == PW_SAMPLER_UNIFORM_NZ ? (d - 1.0) : (1.0 - p0) / f.p;
             for (int a = 0; a < 3; ++a) run[a].add(w * f.m[a]);
@@ -604,6 +687,10 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
         const double se2 = sqrt(run[0].var() / run[0].n);
         const double Mse = se2 / (log(2.0) * S2);
         if (batches >= 2 && target_se > 0 && Mse <= target_se) break;
+    }
+    if (graphs) {
+        PW_HIP(hipEventRecord(c->gjoin, c->gstream));
+        PW_HIP(hipStreamWaitEvent(c->stream, c->gjoin, 0));
     }
     pw_result r;
     memset(&r, 0, sizeof r);
@@ -1017,6 +1104,13 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
     r.L = h.L;
     r.families = h.count;
     *out = r;
+    return PW_OK;
+}
+
+pw_status pw_set_graphs(pw_ctx c, int enable) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    c->use_graphs = enable != 0;
     return PW_OK;
 }
 

@@ -97,11 +97,15 @@ hipError_t apply_gate2(bool dbl, void* psi, int n, int q0, int q1, const double*
 hipError_t apply_diag(bool dbl, void* psi, int n, int q, const double* d2 /*host*/, hipStream_t st);
 
 // Sampling.
-hipError_t sample_uniform(int n, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs, hipStream_t st);
+// With d_off != nullptr the sample counters start at offset + *d_off (read on the
+// device, so that a captured graph draws new samples on every replay).
+hipError_t sample_uniform(int n, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs, hipStream_t st,
+                          const uint64_t* d_off = nullptr);
+hipError_t bump_counter(uint64_t* d_ctr, uint64_t v, hipStream_t st);
 hipError_t build_cdf(bool dbl, const void* psi, int n, double* d_cdf, double* d_blk, hipStream_t st);
 size_t cdf_blk_elems(int n);
 hipError_t sample_marginal(int n, const double* d_cdf, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs,
-                           hipStream_t st);
+                           hipStream_t st, const uint64_t* d_off = nullptr);
 
 // Learned proposal (masked autoregressive network over the bits of x).
 struct MadeDims {

@@ -722,13 +722,18 @@ __global__ void k_signed(const cx<R>* __restrict__ G, int n, uint32_t x, double*
     c[z] = v;
 }
 
-// Launch with optional timing events attached to the dispatch itself.
+// Launch with optional timing events attached to the dispatch itself (sampled
+// launches only; the others are plain launches, which graph capture records).
 #define PW_LAUNCH(TM, KC, NB, KERNEL, GRID, BLOCK, ST, ...)                                      \
     do {                                                                                        \
         hipEvent_t ev0_ = nullptr, ev1_ = nullptr;                                              \
         const bool smp_ = (TM) != nullptr && (TM)->take((TM)->self, (KC), &ev0_, &ev1_);        \
-        hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, ST, ev0_, ev1_, 0u, __VA_ARGS__);          \
-        if (smp_) (TM)->commit((TM)->self, (KC), (NB), ev0_, ev1_);                             \
+        if (smp_) {                                                                             \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, ST, ev0_, ev1_, 0u, __VA_ARGS__);      \
+            (TM)->commit((TM)->self, (KC), (NB), ev0_, ev1_);                                   \
+        } else {                                                                                \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, ST, __VA_ARGS__);                        \
+        }                                                                                       \
     } while (0)
 
 // Tile shapes: first pass and column passes K = 12 (256 threads x 16 points,

@@ -22,9 +22,11 @@ __device__ __forceinline__ void words(uint64_t seed, uint64_t g, uint32_t attemp
     philox_words(seed, g, attempt, stream, W0, W1);
 }
 
-__global__ void k_uniform(int n, uint64_t seed, uint64_t offset, int64_t count, uint64_t* __restrict__ xs) {
+__global__ void k_uniform(int n, uint64_t seed, uint64_t offset, const uint64_t* __restrict__ d_off, int64_t count,
+                          uint64_t* __restrict__ xs) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= count) return;
+    if (d_off) offset += *d_off;
     uint64_t W0, W1;
     words(seed, offset + (uint64_t)i, 0u, STREAM_UNIFORM, W0, W1);
     xs[i] = 1ull + __umul64hi(W0, (1ull << n) - 1ull);
@@ -122,10 +124,11 @@ __device__ __forceinline__ uint64_t upper_bound(const double* __restrict__ C, ui
     return lo;
 }
 
-__global__ void k_marginal(int n, const double* __restrict__ cdf, uint64_t seed, uint64_t offset, int64_t count,
-                           uint64_t* __restrict__ xs) {
+__global__ void k_marginal(int n, const double* __restrict__ cdf, uint64_t seed, uint64_t offset,
+                           const uint64_t* __restrict__ d_off, int64_t count, uint64_t* __restrict__ xs) {
     const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (i >= count) return;
+    if (d_off) offset += *d_off;
     const uint64_t d = 1ull << n;
     const double T = cdf[d - 1];
     uint64_t x = 0;
@@ -138,11 +141,22 @@ __global__ void k_marginal(int n, const double* __restrict__ cdf, uint64_t seed,
     xs[i] = x;
 }
 
+__global__ void k_bump(uint64_t* __restrict__ ctr, uint64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += v;
+}
+
 }  // namespace
 
-hipError_t sample_uniform(int n, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs, hipStream_t st) {
+hipError_t bump_counter(uint64_t* d_ctr, uint64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, st, d_ctr, v);
+    return hipGetLastError();
+}
+
+hipError_t sample_uniform(int n, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs, hipStream_t st,
+                          const uint64_t* d_off) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_uniform, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, n, seed, offset, count, d_xs);
+    hipLaunchKernelGGL(k_uniform, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, n, seed, offset, d_off, count,
+                       d_xs);
     return hipGetLastError();
 }
 
@@ -171,10 +185,10 @@ hipError_t build_cdf(bool dbl, const void* psi, int n, double* d_cdf, double* d_
 }
 
 hipError_t sample_marginal(int n, const double* d_cdf, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs,
-                           hipStream_t st) {
+                           hipStream_t st, const uint64_t* d_off) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_marginal, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, st, n, d_cdf, seed, offset, count,
-                       d_xs);
+    hipLaunchKernelGGL(k_marginal, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, st, n, d_cdf, seed, offset, d_off,
+                       count, d_xs);
     return hipGetLastError();
 }
 

@@ -284,3 +284,20 @@ def test_exact_is_bitwise_reproducible():
     # bitwise: every double and count identical (NaN entries compare as text)
     import json
     assert json.dumps(a, sort_keys=True) == json.dumps(b, sort_keys=True)
+
+
+@pytest.mark.parametrize("n,sampler", [(10, 0), (16, 1), (18, 0)])
+def test_mc_graph_replay_matches_eager(n, sampler):
+    # every replay of the captured sampling step is checked through the estimate it feeds:
+    # graph and eager runs must agree bit for bit (the last, partial batch runs eagerly)
+    import json
+    psi = synth.haar_state(n, 1100 + n)
+    ctx = make_ctx(psi, pw.PW_C128)
+    log("graph replay n=%d sampler=%d" % (n, sampler))
+    eager = ctx.mc(sampler, 1e-7, 32, 32 * 6 + 1 + 7, 0.0, 77)
+    pw.pw_set_graphs(ctx.h, 1)
+    graph = ctx.mc(sampler, 1e-7, 32, 32 * 6 + 1 + 7, 0.0, 77)
+    again = ctx.mc(sampler, 1e-7, 32, 32 * 6 + 1 + 7, 0.0, 77)
+    ctx.close()
+    assert json.dumps(eager, sort_keys=True) == json.dumps(graph, sort_keys=True)
+    assert json.dumps(graph, sort_keys=True) == json.dumps(again, sort_keys=True)
