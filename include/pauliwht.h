@@ -239,6 +239,25 @@ typedef struct {
 } pw_mixed_result;
 PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out);
 
+/* Autotuning of families per launch for the bound state: times evaluation of a run
+ * of consecutive families (4 x the workspace batch) at up to 6 candidate launch sizes
+ * (the workspace batch and its halvings), keeps the fastest for this context and
+ * records it for later binds of the same (device, n, dtype) in this process.
+ * Optional outputs: candidates[i], us_per_family[i] (arrays of >= 6), n_candidates. */
+PW_API pw_status pw_autotune(pw_ctx ctx, int* best_batch, int* candidates, double* us_per_family, int* n_candidates);
+
+/* Several states of different sizes in one call: family xs[i] of state
+ * states[state_idx[i]], results to out[i] (host arrays).  The workspace is carved
+ * once for the largest state and shared; every state is norm-checked.  The bound
+ * state of the context is kept. */
+typedef struct {
+    void* psi;         /* device amplitudes, 256-byte aligned, borrowed */
+    int n;
+    pw_dtype dtype;
+} pw_state_ref;
+PW_API pw_status pw_eval_states(pw_ctx ctx, int nstates, const pw_state_ref* states, const int* state_idx,
+                                const uint64_t* xs, int64_t n_x, double eps, pw_xres* out);
+
 /* Graph replay for pw_mc: when enabled, one sampling step (device-side draws whose
  * counters come from a device counter, evaluation of their families, counter
  * increment) is captured once per pw_mc call as a HIP graph on a private

@@ -20,7 +20,7 @@ __all__ = [
     "PWError", "PW_C128", "PW_C64", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
@@ -70,6 +70,10 @@ class pw_result(ctypes.Structure):
         return out
 
 
+class pw_state_ref(ctypes.Structure):
+    _fields_ = [("psi", ctypes.c_void_p), ("n", ctypes.c_int), ("dtype", ctypes.c_int)]
+
+
 class pw_mixed_result(ctypes.Structure):
     _fields_ = [("W", ctypes.c_double * 3), ("purity", ctypes.c_double), ("S2", ctypes.c_double),
                 ("M", ctypes.c_double * 3), ("L", ctypes.c_double), ("families", ctypes.c_uint64)]
@@ -109,6 +113,8 @@ def _load():
         "pw_mc": ([_vp, _int, _dbl, _int, _u64, _dbl, _u64, ctypes.POINTER(pw_result)], _int),
         "pw_set_moments": ([_vp, _int], _int),
         "pw_set_graphs": ([_vp, _int], _int),
+        "pw_autotune": ([_vp, ctypes.POINTER(_int), _vp, _vp, ctypes.POINTER(_int)], _int),
+        "pw_eval_states": ([_vp, _int, _vp, _vp, _vp, _i64, _dbl, _vp], _int),
         "pw_mixed": ([_vp, _int, _dbl, ctypes.POINTER(pw_mixed_result)], _int),
         "pw_made_param_count": ([_int, _int, ctypes.POINTER(ctypes.c_size_t)], _int),
         "pw_made_init": ([_vp, _int, _int, _vp], _int),
@@ -246,6 +252,31 @@ def pw_mc(ctx, sampler, eps, batch, max_samples, target_se, seed):
 
 def pw_set_moments(ctx, max_alpha):
     _check(_L.pw_set_moments(ctx, int(max_alpha)))
+
+
+def pw_autotune(ctx):
+    """(best families per launch, {candidate: microseconds per family})."""
+    best = _int()
+    cand = (_int * 8)()
+    us = (_dbl * 8)()
+    nc = _int()
+    _check(_L.pw_autotune(ctx, ctypes.byref(best), cand, us, ctypes.byref(nc)))
+    return best.value, {cand[i]: us[i] for i in range(nc.value)}
+
+
+def pw_eval_states(ctx, states, state_idx, xs, eps):
+    """states: list of (device tensor, n, dtype); family xs[i] of states[state_idx[i]]."""
+    arr = (pw_state_ref * len(states))()
+    for k, (t, n, dt) in enumerate(states):
+        arr[k].psi = _ptr(t)
+        arr[k].n = int(n)
+        arr[k].dtype = int(dt)
+    idx = np.ascontiguousarray(state_idx, dtype=np.int32)
+    xs = np.ascontiguousarray(xs, dtype=np.uint64)
+    out = np.zeros(len(xs), dtype=XRES_DTYPE)
+    _check(_L.pw_eval_states(ctx, len(states), arr, idx.ctypes.data, xs.ctypes.data, len(xs), float(eps),
+                             out.ctypes.data))
+    return out
 
 
 def pw_set_graphs(ctx, enable):

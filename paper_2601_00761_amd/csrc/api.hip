@@ -10,7 +10,11 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace pw;
@@ -122,7 +126,8 @@ struct pw_ctx_s {
     int n = 0;
     pw_dtype dtype = PW_C128;
     bool bound = false;
-    int batch = 1;
+    int batch = 1;       // families per launch the workspace is carved for
+    int run_batch = 1;   // families per launch actually used (<= batch; autotuned)
     Layout L{};
     Plan P{};
     bool cdf_valid = false;
@@ -198,6 +203,22 @@ void timer_commit(void* self, int k, int families, hipEvent_t a, hipEvent_t b) {
 
 const LaunchTimer* timer_of(pw_ctx c) { return (c->timing_every > 0 && !c->capturing) ? &c->timer : nullptr; }
 
+// Autotuned families-per-launch, per (device, n, dtype), shared by the contexts of
+// the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;
+
+int tuned_batch(int device, int n, pw_dtype dt) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(device, n, (int)dt));
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+void set_tuned_batch(int device, int n, pw_dtype dt, int b) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(device, n, (int)dt)] = b;
+}
+
 pw_status check_ctx(pw_ctx c) {
     if (!c) return fail(PW_ERR_ARG, "null context");
     return PW_OK;
@@ -244,6 +265,9 @@ pw_status prepare_workspace(pw_ctx c, int n, pw_dtype dt) {
     }
     c->L = layout_for(n, dt, c->batch);
     c->P = make_plan(n, dt == PW_C128);
+    c->run_batch = c->batch;
+    const int tuned = tuned_batch(c->device, n, dt);
+    if (tuned > 0 && tuned < c->batch) c->run_batch = tuned;
     return PW_OK;
 }
 
@@ -270,8 +294,8 @@ pw_status run_norm(pw_ctx c, double* out) {
 pw_status eval_device(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out) {
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
     const bool dbl = c->dtype == PW_C128;
-    for (int64_t i = 0; i < nx; i += c->batch) {
-        const int nb = (int)((nx - i) < c->batch ? (nx - i) : c->batch);
+    for (int64_t i = 0; i < nx; i += c->run_batch) {
+        const int nb = (int)((nx - i) < c->run_batch ? (nx - i) : c->run_batch);
         PW_HIP(eval_batch(c->P, dbl, c->max_alpha, c->psi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
                           c->ws + c->L.work, at<FamilyRes>(c, c->L.parts), d_out + i, c->stream, timer_of(c)));
     }
@@ -1104,6 +1128,167 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
     r.L = h.L;
     r.families = h.count;
     *out = r;
+    return PW_OK;
+}
+
+pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per_family, int* n_candidates) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (!best_batch) return fail(PW_ERR_ARG, "null output");
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    // candidate families per launch: powers of two up to the workspace batch
+    std::vector<int> cand;
+    for (int b = c->batch; b >= 1 && (int)cand.size() < 6; b /= 2) cand.push_back(b);
+    const uint64_t d = 1ull << c->n;
+    const int64_t total = (int64_t)((uint64_t)(4 * c->batch) < d ? (uint64_t)(4 * c->batch) : d);
+    const uint64_t x0 = d > (uint64_t)(2 * total) ? (d >> 1) : 0;   // a run of consecutive families
+    hipEvent_t e0, e1;
+    PW_HIP(hipEventCreate(&e0));
+    PW_HIP(hipEventCreate(&e1));
+    const int saved = c->run_batch;
+    const int saved_every = c->timing_every;
+    c->timing_every = 0;
+    double best = 1e300;
+    int bestb = c->batch;
+    std::vector<double> times;
+    FamilyRes* fam = at<FamilyRes>(c, c->L.fam);
+    for (int b : cand) {
+        c->run_batch = b;
+        double tmin = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {   // first repetition warms up
+            PW_HIP(hipEventRecord(e0, c->stream));
+            s = eval_device(c, nullptr, x0, total, 1e-4, fam);
+            if (s != PW_OK) break;
+            PW_HIP(hipEventRecord(e1, c->stream));
+            PW_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) tmin = fmin(tmin, (double)ms);
+        }
+        if (s != PW_OK) break;
+        const double us = 1e3 * tmin / (double)total;
+        times.push_back(us);
+        if (us < best) {
+            best = us;
+            bestb = b;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing_every = saved_every;
+    if (s != PW_OK) {
+        c->run_batch = saved;
+        return s;
+    }
+    c->run_batch = bestb;
+    set_tuned_batch(c->device, c->n, c->dtype, bestb);
+    *best_batch = bestb;
+    if (n_candidates) *n_candidates = (int)times.size();
+    for (size_t i = 0; i < times.size(); ++i) {
+        if (candidates) candidates[i] = cand[i];
+        if (us_per_family) us_per_family[i] = times[i];
+    }
+    return PW_OK;
+}
+
+pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, const int* state_idx,
+                         const uint64_t* xs, int64_t n_x, double eps, pw_xres* out) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (nstates < 1 || !states) return fail(PW_ERR_ARG, "no states");
+    if (n_x < 0 || (n_x > 0 && (!state_idx || !xs || !out))) return fail(PW_ERR_ARG, "bad arrays");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
+    for (int k = 0; k < nstates; ++k) {
+        const pw_state_ref& r = states[k];
+        if (!r.psi || ((uintptr_t)r.psi & 255)) return fail(PW_ERR_ARG, "state %d: null or unaligned pointer", k);
+        if (r.dtype != PW_C128 && r.dtype != PW_C64) return fail(PW_ERR_ARG, "state %d: unknown dtype", k);
+        if (r.n < 1 || r.n > MAX_QUBITS) return fail(PW_ERR_RANGE, "state %d: n=%d outside [1, %d]", k, r.n, MAX_QUBITS);
+    }
+    for (int64_t i = 0; i < n_x; ++i) {
+        if (state_idx[i] < 0 || state_idx[i] >= nstates) return fail(PW_ERR_ARG, "state_idx[%lld] out of range", (long long)i);
+        if (xs[i] >> states[state_idx[i]].n) return fail(PW_ERR_RANGE, "xs[%lld] not below 2^n of its state", (long long)i);
+    }
+    // one workspace carve shared by all states: the batch of the most demanding state,
+    // and room for the largest layout at that batch
+    int B = MAX_BATCH;
+    for (int k = 0; k < nstates; ++k) B = std::min(B, default_batch(states[k].n, states[k].dtype));
+    auto need_for = [&](int b) {
+        size_t need = 0;
+        for (int k = 0; k < nstates; ++k) need = std::max(need, layout_for(states[k].n, states[k].dtype, b).total);
+        return need;
+    };
+    if (c->ws && !c->ws_owned) {
+        while (B > 1 && need_for(B) > c->ws_bytes) B /= 2;
+        if (need_for(B) > c->ws_bytes) return fail(PW_ERR_WORKSPACE, "workspace too small for the largest state");
+    } else if (!c->ws || c->ws_bytes < need_for(B)) {
+        if (c->ws) {
+            PW_HIP(hipStreamSynchronize(c->stream));
+            PW_HIP(hipFree(c->ws));
+            c->ws = nullptr;
+            c->ws_bytes = 0;
+        }
+        if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+        void* p = nullptr;
+        PW_HIP(hipMalloc(&p, need_for(B)));
+        c->ws = (char*)p;
+        c->ws_bytes = need_for(B);
+        c->ws_owned = true;
+    }
+    const bool was_bound = c->bound;
+    void* const saved_psi = c->psi;
+    const int saved_n = c->n;
+    const pw_dtype saved_dt = c->dtype;
+    const size_t cap = c->ws_bytes;
+    std::vector<FamilyRes> res((size_t)n_x);
+    std::vector<uint64_t> sx;
+    std::vector<int64_t> pos;
+    for (int k = 0; k < nstates && s == PW_OK; ++k) {
+        sx.clear();
+        pos.clear();
+        for (int64_t i = 0; i < n_x; ++i)
+            if (state_idx[i] == k) {
+                sx.push_back(xs[i]);
+                pos.push_back(i);
+            }
+        if (sx.empty()) continue;
+        c->psi = states[k].psi;
+        c->n = states[k].n;
+        c->dtype = states[k].dtype;
+        c->P = make_plan(c->n, c->dtype == PW_C128);
+        c->L = layout_for(c->n, c->dtype, B);
+        if (c->L.total > cap) {
+            s = fail(PW_ERR_WORKSPACE, "state %d does not fit the shared workspace", k);
+            break;
+        }
+        c->batch = B;
+        c->run_batch = B;
+        c->cdf_valid = false;
+        double nrm = 0.0;
+        s = run_norm(c, &nrm);
+        if (s != PW_OK) break;
+        const double tol = c->dtype == PW_C128 ? 1e-10 : 1e-5;
+        if (!(fabs(nrm - 1.0) <= tol)) {
+            s = fail(PW_ERR_NOT_NORMALIZED, "state %d: <psi|psi> = %.17g", k, nrm);
+            break;
+        }
+        std::vector<FamilyRes> r(sx.size());
+        s = eval_host(c, sx.data(), (int64_t)sx.size(), eps, r.data());
+        if (s != PW_OK) break;
+        for (size_t j = 0; j < sx.size(); ++j) res[pos[j]] = r[j];
+    }
+    // restore the bound state (the workspace stays carved for the largest)
+    c->psi = saved_psi;
+    c->n = saved_n;
+    c->dtype = saved_dt;
+    c->bound = false;
+    c->cdf_valid = false;
+    if (was_bound) {
+        pw_status s2 = prepare_workspace(c, saved_n, saved_dt);
+        if (s2 == PW_OK) c->bound = true;
+        if (s == PW_OK) s = s2;
+    }
+    if (s != PW_OK) return s;
+    memcpy(out, res.data(), (size_t)n_x * sizeof(FamilyRes));
     return PW_OK;
 }
 

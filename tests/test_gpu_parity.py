@@ -301,3 +301,47 @@ def test_mc_graph_replay_matches_eager(n, sampler):
     ctx.close()
     assert json.dumps(eager, sort_keys=True) == json.dumps(graph, sort_keys=True)
     assert json.dumps(graph, sort_keys=True) == json.dumps(again, sort_keys=True)
+
+
+def test_eval_states_uneven_sizes_match_single_state_calls():
+    import torch
+    sizes = [(9, 0), (12, 1), (15, 0), (16, 1), (17, 0), (18, 1)]
+    states, tensors, refs = [], [], []
+    for k, (n, dt) in enumerate(sizes):
+        psi = as_input(synth.haar_state(n, 1200 + k), dt)
+        t = torch.tensor(psi.astype(np.complex128 if dt == 0 else np.complex64), device="cuda:0")
+        tensors.append(t)
+        states.append((t, n, dt))
+        refs.append(psi)
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, len(sizes), 60).astype(np.int32)
+    xs = np.array([int(rng.integers(0, 1 << sizes[i][0])) for i in idx], dtype=np.uint64)
+    log("eval_states %d states, %d families" % (len(sizes), len(xs)))
+    ctx = pw.Context(0)
+    got = pw.pw_eval_states(ctx.h, states, idx, xs, 1e-6)
+    for k, (n, dt) in enumerate(sizes):
+        sel = np.nonzero(idx == k)[0]
+        if len(sel) == 0:
+            continue
+        ctx.bind(tensors[k], dt)
+        single = ctx.eval_x(xs[sel], 1e-6)
+        assert np.array_equal(got[sel].view(np.uint8), single.view(np.uint8))
+        if dt == 0:
+            r = oracle.eval_x(refs[k], xs[sel], eps=1e-6)
+            assert np.allclose(got["m"][sel, 0], r["m"][:, 0], rtol=1e-10, atol=0)
+    ctx.close()
+
+
+def test_autotune_picks_a_candidate_and_keeps_results():
+    n = 18
+    psi = synth.haar_state(n, 1300).astype(np.complex64)
+    ctx = make_ctx(psi, pw.PW_C64)
+    before = ctx.exact(1e-4)
+    best, table = pw.pw_autotune(ctx.h)
+    log("autotune n=%d best=%d table=%s" % (n, best, table))
+    after = ctx.exact(1e-4)
+    ctx.close()
+    assert best in table and all(v > 0 for v in table.values())
+    for a in range(1):
+        assert abs(after["S"][a] / before["S"][a] - 1) < 1e-12
+    assert after["nu_cnt"] == before["nu_cnt"]
