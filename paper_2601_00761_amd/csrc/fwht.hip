@@ -93,6 +93,37 @@ __device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<
     __syncthreads();
 }
 
+// The same move for tiles too large for one complex LDS buffer (2^15 single-
+// precision points = 256 KB > 160 KB): real parts first, then imaginary parts,
+// through a float buffer padded one element in 32.
+__host__ __device__ constexpr uint32_t pad32c(uint32_t i) { return i + (i >> 5); }
+
+template <typename R, int TL, int RL, int AO, int AN>
+__device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL], R* buf) {
+    const uint32_t tid = threadIdx.x;
+    R* wo = buf + pad32c(thread_part<AO, RL>(tid));
+    const R* rn = buf + pad32c(thread_part<AN, RL>(tid));
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) wo[pad32c((uint32_t)j << AO)] = re[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) re[j] = rn[pad32c((uint32_t)j << AN)];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) wo[pad32c((uint32_t)j << AO)] = im[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) im[j] = rn[pad32c((uint32_t)j << AN)];
+    __syncthreads();
+}
+
+// LDS bytes of a tile of 2^K points.
+template <typename R, int K, bool SPLIT>
+struct LdsBytes {
+    static constexpr size_t v = SPLIT ? ((size_t)(1 << K) + ((1 << K) >> 5)) * sizeof(R)
+                                      : ((size_t)(1 << K) + ((1 << K) >> 4)) * sizeof(cx<R>);
+};
+
 // After the first round (window TL, register bits [max(TL, LO), K)), the bits
 // [LO, TL) are taken in blocks of RL from the bottom: window B0 transforms
 // [B0, min(B0 + RL, TL)).  The result stays in the last window, whose low
@@ -105,25 +136,26 @@ constexpr int final_window() {
     return b0;
 }
 
-template <typename R, int TL, int RL, int A, int B0>
+template <typename R, int TL, int RL, int A, int B0, bool SPLIT>
 struct Rounds {
-    static __device__ __forceinline__ void run(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds) {
+    static __device__ __forceinline__ void run(R (&re)[1 << RL], R (&im)[1 << RL], void* lds) {
         if constexpr (B0 < TL) {
-            exchange<R, TL, RL, A, B0>(re, im, lds);
+            if constexpr (SPLIT) exchange_split<R, TL, RL, A, B0>(re, im, (R*)lds);
+            else exchange<R, TL, RL, A, B0>(re, im, (cx<R>*)lds);
             constexpr int B1 = (B0 + RL < TL) ? B0 + RL : TL;
             reg_stages<R, RL, 0, B1 - B0>(re, im);
-            Rounds<R, TL, RL, B0, B0 + RL>::run(re, im, lds);
+            Rounds<R, TL, RL, B0, B0 + RL, SPLIT>::run(re, im, lds);
         }
     }
 };
 
 // Unnormalised WHT over bits [LO, K) of the tile index.  On entry thread t holds
 // points t + j 2^TL (window TL); on exit the points are in final_window().
-template <typename R, int TL, int RL, int LO>
-__device__ __forceinline__ void tile_fwht(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds) {
+template <typename R, int TL, int RL, int LO, bool SPLIT = false>
+__device__ __forceinline__ void tile_fwht(R (&re)[1 << RL], R (&im)[1 << RL], void* lds) {
     constexpr int S0 = LO > TL ? LO : TL;
     reg_stages<R, RL, S0 - TL, RL>(re, im);
-    Rounds<R, TL, RL, TL, LO>::run(re, im, lds);
+    Rounds<R, TL, RL, TL, LO, SPLIT>::run(re, im, lds);
 }
 
 // f values of the half-size problem at half indices (tile << K) + t + j 2^TL
@@ -502,19 +534,19 @@ __device__ __forceinline__ void store_tile(cx<R>* __restrict__ dst, const R (&re
 
 // First pass of a multi-pass transform: products + low K index bits of one tile.
 // Grid: (tiles per family, families).
-template <typename R, int TL, int RL>
+template <typename R, int TL, int RL, bool SPLIT = false>
 __global__ void __launch_bounds__(1 << TL)
 k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0,
         cx<R>* __restrict__ work) {
     constexpr int K = TL + RL;
-    __shared__ cx<R> lds[Lds<K>::elems];
+    __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT>::v];
     const int nh = n - 1;
     const uint32_t tile = blockIdx.x, slot = blockIdx.y;
     const uint32_t x = (uint32_t)(xs ? xs[slot] : x0 + slot);
     R re[1 << RL], im[1 << RL];
     if (x >= (1u << K)) load_products_hi<R, TL, RL>(psi, x, tile, re, im);
     else load_products<R, TL, RL>(psi, nh, x, tile, re, im);
-    tile_fwht<R, TL, RL, 0>(re, im, lds);
+    tile_fwht<R, TL, RL, 0, SPLIT>(re, im, lds);
     store_tile<R, TL, RL>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
 }
 
@@ -575,17 +607,22 @@ k_first_shared(const cx<R>* __restrict__ psi, int n, uint64_t x0, int fam, cx<R>
 // A tile is 2^S rows (stride 2^lo) by 2^W consecutive columns, W = K - S.
 // Grid: (2^(nh - K), families).  LAST: reduce to one partial per workgroup
 // (parts[family][block]) instead of writing the spectrum back.
-template <typename R, int TL, int RL, int S, bool LAST, int MOM>
+template <typename R, int TL, int RL, int S, bool LAST, int MOM, bool SPLIT = false>
 __global__ void __launch_bounds__(1 << TL)
 k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
          FamilyRes* __restrict__ parts) {
     constexpr int K = TL + RL;
     constexpr int NT = 1 << TL;
     constexpr int W = K - S;
-    __shared__ cx<R> lds[Lds<K>::elems];
+    __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT>::v];
     const int nh = n - 1;
     const int cbits = lo - W;
-    const uint32_t bid = blockIdx.x, slot = blockIdx.y;
+    // Workgroups are dealt round-robin to the 8 XCDs; when a family has a multiple of
+    // 8 blocks, renumber them so that each XCD takes a contiguous range of column
+    // blocks and neighbouring (partial-cache-line) columns share its L2.
+    const uint32_t G = gridDim.x;
+    const uint32_t bid = (G & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    const uint32_t slot = blockIdx.y;
     const uint32_t cb = bid & ((1u << cbits) - 1u);
     const uint32_t hb = bid >> cbits;
     cx<R>* base = work + ((size_t)slot << nh) + ((size_t)hb << (lo + S)) + ((size_t)cb << W);
@@ -603,7 +640,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
         re[j] = v.re;
         im[j] = v.im;
     }
-    tile_fwht<R, TL, RL, W>(re, im, lds);
+    tile_fwht<R, TL, RL, W, SPLIT>(re, im, lds);
     if constexpr (!LAST) {
         constexpr int A = final_window<TL, RL, W>();
         const uint32_t T = thread_part<A, RL>(tid);
@@ -620,7 +657,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
         __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
         const uint64_t x = xs ? xs[slot] : x0 + slot;
         const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
-        if (threadIdx.x == 0) parts[(size_t)slot * gridDim.x + bid] = raw_res(tot, x);
+        if (threadIdx.x == 0) parts[(size_t)slot * G + bid] = raw_res(tot, x);
     }
 }
 
@@ -810,12 +847,31 @@ hipError_t launch_column_t(int s, dim3 grid, cx<R>* work, int n, int lo, const u
     }
 }
 
+// Column pass over a 15-bit single-precision tile (1024 threads x 32 points, split
+// LDS exchange): rows of 2^(15 - s) points, s = 9..12.
+template <bool LAST, int MOM>
+hipError_t launch_column15(int s, dim3 grid, cx<float>* work, int n, int lo, const uint64_t* xs, uint64_t x0,
+                           float eps, FamilyRes* parts, hipStream_t st, const LaunchTimer* tm) {
+    const int kc = LAST ? 3 : 2;
+    switch (s) {
+#define PW_COL15(S)                                                                                                \
+    case S:                                                                                                        \
+        PW_LAUNCH(tm, kc, (int)grid.y, (k_column<float, 10, 5, S, LAST, MOM, true>), grid, dim3(1024), st, work, n, \
+                  lo, xs, x0, eps, parts);                                                                         \
+        return hipGetLastError();
+        PW_COL15(9) PW_COL15(10) PW_COL15(11) PW_COL15(12)
+#undef PW_COL15
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R, bool LAST, int MOM>
 hipError_t launch_column(int ktile, int s, int nh, int nb, cx<R>* work, int n, int lo, const uint64_t* xs,
                          uint64_t x0, R eps, FamilyRes* parts, hipStream_t st, const LaunchTimer* tm) {
     const dim3 grid(1u << (nh - ktile), nb);
     if constexpr (sizeof(R) == 4) {
         if (ktile == 13) return launch_column_t<R, 9, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st, tm);
+        if (ktile == 15) return launch_column15<LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st, tm);
     }
     if (ktile != 12) return hipErrorInvalidValue;
     return launch_column_t<R, 8, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st, tm);
@@ -827,7 +883,14 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
     if (nb <= 0) return hipSuccess;
     const R e = (R)eps;
     if (P.fused) return launch_fused<R, MOM>(psi, P.n, xs, x0, nb, e, out, st, tm);
-    const uint32_t tiles = 1u << (P.nh - K_FIRST);
+    const uint32_t tiles = 1u << (P.nh - P.k1);
+    if constexpr (sizeof(R) == 4) {
+        if (P.k1 == 15) {
+            PW_LAUNCH(tm, 1, nb, (k_first<float, 10, 5, true>), dim3(tiles, nb), dim3(1024), st, (const cx<float>*)psi,
+                      P.n, xs, x0, (cx<float>*)work);
+            goto first_done;
+        }
+    }
     if (!xs && x0 >= (1ull << K_FIRST) && (x0 >> 8) == ((x0 + nb - 1) >> 8) && (x0 % nb) == 0) {
         // a run of consecutive families inside one 256-aligned block: share the state tiles
         int fam = 1;
@@ -838,6 +901,7 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
         PW_LAUNCH(tm, 1, nb, (k_first<R, 8, 4>), dim3(tiles, nb), dim3(256), st, (const cx<R>*)psi, P.n, xs, x0,
                   (cx<R>*)work);
     }
+first_done:
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
@@ -857,8 +921,17 @@ hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* wor
     // the multi-pass schedule without the final reduction
     const int nh = P.nh;
     if (P.fused || nh <= K_FIRST) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (nh - K_FIRST), 1), dim3(256), 0, st, (const cx<R>*)psi, P.n,
-                       (const uint64_t*)nullptr, x, (cx<R>*)work);
+    bool done = false;
+    if constexpr (sizeof(R) == 4) {
+        if (P.k1 == 15) {
+            hipLaunchKernelGGL((k_first<float, 10, 5, true>), dim3(1u << (nh - 15), 1), dim3(1024), 0, st,
+                               (const cx<float>*)psi, P.n, (const uint64_t*)nullptr, x, (cx<float>*)work);
+            done = true;
+        }
+    }
+    if (!done)
+        hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (nh - K_FIRST), 1), dim3(256), 0, st, (const cx<R>*)psi,
+                           P.n, (const uint64_t*)nullptr, x, (cx<R>*)work);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
@@ -884,6 +957,16 @@ Plan make_plan(int n, bool dbl) {
         return P;
     }
     P.fused = false;
+    if (!dbl && P.nh >= 22 && P.nh <= 27) {
+        // single precision, n = 23..28: a 15-bit first pass leaves one column pass
+        P.k1 = 15;
+        P.npass = 1;
+        P.lo[0] = 15;
+        P.s[0] = P.nh - 15;
+        P.ktile = P.s[0] <= 8 ? 12 : 15;
+        P.blocks_last = 1 << (P.nh - P.ktile);
+        return P;
+    }
     P.k1 = K_FIRST;
     const int rem = P.nh - K_FIRST;
     // column tiles of 2^ktile points with rows of >= 128 bytes: s <= ktile - 4 (single),
