@@ -519,17 +519,41 @@ k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
         }
 }
 
-template <typename R, int TL, int RL>
+// Intermediate tiles of the 2^15-point plans belong to families of 2^21 and more
+// points, far beyond what the caches hold between passes: those passes move them
+// with streaming (nontemporal) loads and stores.  Smaller plans keep the default
+// policy, under which part of a batch is still cached when the next pass reads it.
+template <bool STREAM, typename R>
+__device__ __forceinline__ void st_point(cx<R>* p, R re, R im) {
+    if constexpr (STREAM) {
+        __builtin_nontemporal_store(re, &p->re);
+        __builtin_nontemporal_store(im, &p->im);
+    } else {
+        cx<R> v;
+        v.re = re;
+        v.im = im;
+        *p = v;
+    }
+}
+
+template <bool STREAM, typename R>
+__device__ __forceinline__ void ld_point(const cx<R>* p, R& re, R& im) {
+    if constexpr (STREAM) {
+        re = __builtin_nontemporal_load(&p->re);
+        im = __builtin_nontemporal_load(&p->im);
+    } else {
+        const cx<R> v = *p;
+        re = v.re;
+        im = v.im;
+    }
+}
+
+template <typename R, int TL, int RL, bool STREAM = false>
 __device__ __forceinline__ void store_tile(cx<R>* __restrict__ dst, const R (&re)[1 << RL], const R (&im)[1 << RL]) {
     constexpr int A = final_window<TL, RL, 0>();
     cx<R>* p = dst + thread_part<A, RL>(threadIdx.x);
 #pragma unroll
-    for (int j = 0; j < (1 << RL); ++j) {
-        cx<R> v;
-        v.re = re[j];
-        v.im = im[j];
-        p[(uint32_t)j << A] = v;
-    }
+    for (int j = 0; j < (1 << RL); ++j) st_point<STREAM>(p + ((uint32_t)j << A), re[j], im[j]);
 }
 
 // First pass of a multi-pass transform: products + low K index bits of one tile.
@@ -547,7 +571,7 @@ k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     if (x >= (1u << K)) load_products_hi<R, TL, RL>(psi, x, tile, re, im);
     else load_products<R, TL, RL>(psi, nh, x, tile, re, im);
     tile_fwht<R, TL, RL, 0, SPLIT>(re, im, lds);
-    store_tile<R, TL, RL>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
+    store_tile<R, TL, RL, SPLIT>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
 }
 
 // First pass for a run of consecutive families x0 + i that share x >> K != 0
@@ -636,9 +660,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) {
         const uint32_t J = (uint32_t)j << TL;
-        const cx<R> v = pin[(J & WM) + ((size_t)(J >> W) << lo)];
-        re[j] = v.re;
-        im[j] = v.im;
+        ld_point<SPLIT>(pin + (J & WM) + ((size_t)(J >> W) << lo), re[j], im[j]);
     }
     tile_fwht<R, TL, RL, W, SPLIT>(re, im, lds);
     if constexpr (!LAST) {
@@ -648,10 +670,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
             const uint32_t J = (uint32_t)j << A;
-            cx<R> v;
-            v.re = re[j];
-            v.im = im[j];
-            pout[(J & WM) + ((size_t)(J >> W) << lo)] = v;
+            st_point<SPLIT>(pout + (J & WM) + ((size_t)(J >> W) << lo), re[j], im[j]);
         }
     } else {
         __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
