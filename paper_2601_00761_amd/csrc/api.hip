@@ -61,7 +61,13 @@ size_t esize(pw_dtype dt) { return dt == PW_C128 ? 16 : 8; }
 // Workspace layout for (n, dtype, batch).
 struct Layout {
     size_t work, parts, xs, xres, fam, sweep, cdf, cdfblk, norm, ctr, total;
+    int64_t parts_fams;  // families whose final-pass partials the parts region holds
 };
+
+// Partials of several batches are kept (up to 16 batches, 16 MiB) so that one
+// finalize launch serves them all.
+constexpr size_t PARTS_BYTES_MAX = (size_t)16 << 20;
+constexpr int PARTS_GROUP_MAX = 16;
 
 Layout layout_for(int n, pw_dtype dt, int batch) {
     const bool dbl = dt == PW_C128;
@@ -77,7 +83,12 @@ Layout layout_for(int n, pw_dtype dt, int batch) {
     L.work = off;
     off += align256(work);
     L.parts = off;
-    off += align256((size_t)batch * (size_t)P.blocks_last * sizeof(FamilyRes));
+    const size_t per_batch = (size_t)batch * (size_t)P.blocks_last * sizeof(FamilyRes);
+    size_t group = P.fused ? 1 : PARTS_BYTES_MAX / per_batch;
+    if (group < 1) group = 1;
+    if (group > (size_t)PARTS_GROUP_MAX) group = PARTS_GROUP_MAX;
+    L.parts_fams = (int64_t)group * batch;
+    off += align256(group * per_batch);
     L.xs = off;
     off += align256((size_t)batch * sizeof(uint64_t));
     L.xres = off;
@@ -294,11 +305,23 @@ pw_status run_norm(pw_ctx c, double* out) {
 pw_status eval_device(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out) {
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
     const bool dbl = c->dtype == PW_C128;
+    // multi-pass plans: batches leave their partials side by side, one finalize per group
+    const bool defer = !c->P.fused;
+    FamilyRes* parts = at<FamilyRes>(c, c->L.parts);
+    int64_t g0 = 0, pending = 0;
     for (int64_t i = 0; i < nx; i += c->run_batch) {
         const int nb = (int)((nx - i) < c->run_batch ? (nx - i) : c->run_batch);
+        if (defer && pending + nb > c->L.parts_fams) {
+            PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, c->stream));
+            g0 = i;
+            pending = 0;
+        }
         PW_HIP(eval_batch(c->P, dbl, c->max_alpha, c->psi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
-                          c->ws + c->L.work, at<FamilyRes>(c, c->L.parts), d_out + i, c->stream, timer_of(c)));
+                          c->ws + c->L.work, parts + (size_t)pending * c->P.blocks_last, d_out + i, c->stream,
+                          timer_of(c), !defer));
+        pending += nb;
     }
+    if (defer && pending > 0) PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, c->stream));
     return PW_OK;
 }
 

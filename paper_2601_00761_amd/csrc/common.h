@@ -68,9 +68,15 @@ struct LaunchTimer {
 // Evaluate a batch of nb families.  If xs != nullptr the x of slot i is xs[i],
 // else it is x0 + i.  Per-family results go to out[i].  max_alpha is 2 (moments
 // alpha = 2 only; m[1], m[2] are NaN) or 4.  parts holds nb * blocks_last partials.
+// With finalize == false a multi-pass plan stops at the partials (family i at
+// parts + i * blocks_last) and out is not written: several batches can then be
+// finalized by one finalize_families call.  Single-workgroup plans always write out.
 hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, const uint64_t* xs, uint64_t x0,
                       int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
-                      const LaunchTimer* tm = nullptr);
+                      const LaunchTimer* tm = nullptr, bool finalize = true);
+// Per-family results of nfam families whose partials are contiguous in parts.
+hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* parts, int64_t nfam, FamilyRes* out,
+                             hipStream_t st);
 
 // Mixed states: rho_A = Psi Psi^dagger of the first na qubits (d_A x d_A, row-major),
 // and the families x_A = x0 .. x0 + nb - 1 of the reduced state (na - 1 <= 13 / 12).

@@ -898,7 +898,8 @@ hipError_t launch_column(int ktile, int s, int nh, int nb, cx<R>* work, int n, i
 
 template <typename R, int MOM>
 hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, double eps,
-                        void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st, const LaunchTimer* tm) {
+                        void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st, const LaunchTimer* tm,
+                        bool finalize) {
     if (nb <= 0) return hipSuccess;
     const R e = (R)eps;
     if (P.fused) return launch_fused<R, MOM>(psi, P.n, xs, x0, nb, e, out, st, tm);
@@ -931,6 +932,7 @@ first_done:
                                                 parts, st, tm);
         if (err != hipSuccess) return err;
     }
+    if (!finalize) return hipSuccess;
     hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
     return hipGetLastError();
 }
@@ -1013,12 +1015,23 @@ Plan make_plan(int n, bool dbl) {
 
 hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, const uint64_t* xs, uint64_t x0,
                       int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
-                      const LaunchTimer* tm) {
+                      const LaunchTimer* tm, bool finalize) {
     if (dbl)
-        return max_alpha >= 4 ? eval_batch_t<double, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm)
-                              : eval_batch_t<double, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm);
-    return max_alpha >= 4 ? eval_batch_t<float, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm)
-                          : eval_batch_t<float, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm);
+        return max_alpha >= 4 ? eval_batch_t<double, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize)
+                              : eval_batch_t<double, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize);
+    return max_alpha >= 4 ? eval_batch_t<float, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize)
+                          : eval_batch_t<float, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize);
+}
+
+hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* parts, int64_t nfam, FamilyRes* out,
+                             hipStream_t st) {
+    if (P.fused || nfam <= 0) return hipSuccess;
+    if (nfam > 0x7fffffff) return hipErrorInvalidValue;
+    if (max_alpha >= 4)
+        hipLaunchKernelGGL((k_finalize<4>), dim3((unsigned)nfam), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
+    else
+        hipLaunchKernelGGL((k_finalize<2>), dim3((unsigned)nfam), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
+    return hipGetLastError();
 }
 
 hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st) {
