@@ -574,18 +574,54 @@ k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     store_tile<R, TL, RL, SPLIT>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
 }
 
-// First pass for a run of consecutive families x0 + i that share x >> K != 0
-// (exact sweeps): the state tile tu << K and its partner (tu ^ (x >> K)) << K
-// are the same for the whole run, so a workgroup loads them once (own tile in
-// registers, partner tile in LDS) and forms, transforms and writes `fam`
-// families in turn.  The partner tile is stored with its register-block index
-// XORed by (x mod 2^K) >> TL, constant over the run, so that every family reads
-// it at a per-thread base plus immediate offsets.  Grid: (tiles, run / fam).
+// v from lane (lane XOR 2^B) of the same wave, B < 4, by DPP row permutations
+// (plain VALU moves, no LDS): xor 1 and xor 2 are quad permutations, xor 8 is a
+// rotation of the 16-lane row by 8, xor 4 is the 8-lane mirror (xor 7) followed
+// by the quad reversal (xor 3).
+template <int B>
+__device__ __forceinline__ uint32_t dpp_xor(uint32_t w) {
+    const int v = (int)w;
+    if constexpr (B == 0) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+    if constexpr (B == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+    if constexpr (B == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true),
+                                                                    0x1B, 0xF, 0xF, true);
+    if constexpr (B == 3) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);
+    return w;
+}
+
+template <int B, typename R>
+__device__ __forceinline__ R lane_xor(R v) {
+    constexpr int NW = sizeof(R) / 4;
+    uint32_t w[NW];
+    __builtin_memcpy(w, &v, sizeof(R));
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = dpp_xor<B>(w[k]);
+    __builtin_memcpy(&v, w, sizeof(R));
+    return v;
+}
+
+template <int B, typename R, int RL>
+__device__ __forceinline__ void regs_lane_xor(R (&vr)[1 << RL], R (&vi)[1 << RL]) {
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) {
+        vr[j] = lane_xor<B>(vr[j]);
+        vi[j] = lane_xor<B>(vi[j]);
+    }
+}
+
+// First pass for a run of fam <= 16 consecutive families x = x_r + f (x_r a
+// multiple of fam, f < fam) that share x >> K != 0 (exact sweeps).  The state
+// tile tu << K and its partner (tu ^ (x >> K)) << K are the same for the whole
+// run and both stay in registers: thread t holds psi at t of its own tile and at
+// (t ^ (x_r mod 2^TL)) + ((j ^ jx) << TL) of the partner tile, jx = (x_r mod 2^K) >> TL.
+// Family f needs the partner value of lane t ^ f, in the same 16-lane row; the
+// families are taken in Gray-code order so that each step moves the partner
+// registers by one lane XOR.  Grid: (tiles, run / fam).
 template <typename R, int TL, int RL>
 __global__ void __launch_bounds__(1 << TL)
 k_first_shared(const cx<R>* __restrict__ psi, int n, uint64_t x0, int fam, cx<R>* __restrict__ work) {
     constexpr int K = TL + RL;
-    __shared__ cx<R> vt[1 << K];
+    static_assert(TL >= 6, "a 16-lane row must lie inside one wave");
     __shared__ cx<R> lds[Lds<K>::elems];
     const int nh = n - 1;
     const uint32_t tile = blockIdx.x, grp = blockIdx.y;
@@ -596,34 +632,41 @@ k_first_shared(const cx<R>* __restrict__ psi, int n, uint64_t x0, int fam, cx<R>
     const uint32_t lowm = (1u << q) - 1u;
     const uint32_t tu = (tile & lowm) | ((tile & ~lowm) << 1);
     const uint32_t tv = tu ^ xh;
+    const uint32_t c = xr & ((1u << TL) - 1u);
     const uint32_t jx = (xr & ((1u << K) - 1u)) >> TL;
     const uint32_t tid = threadIdx.x;
-    R ur[1 << RL], ui[1 << RL];
+    R ur[1 << RL], ui[1 << RL], vr[1 << RL], vi[1 << RL];
     {
         const cx<R>* pa = psi + ((size_t)tu << K) + tid;
-        const cx<R>* pv = psi + ((size_t)tv << K) + tid;
+        const cx<R>* pv = psi + ((size_t)tv << K) + (tid ^ c);
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
             const cx<R> u = pa[(uint32_t)j << TL];
+            const cx<R> v = pv[((uint32_t)j ^ jx) << TL];
             ur[j] = u.re;
             ui[j] = u.im;
-            vt[tid + (((uint32_t)j ^ jx) << TL)] = pv[(uint32_t)j << TL];
+            vr[j] = v.re;
+            vi[j] = v.im;
         }
     }
-    __syncthreads();
-    for (int f = 0; f < fam; ++f) {
-        const uint32_t slot = slot0 + (uint32_t)f;
-        const uint32_t xlo = (uint32_t)(x0 + slot) & ((1u << TL) - 1u);
-        const cx<R>* pv = vt + (tid ^ xlo);
+    for (int k = 0; k < fam; ++k) {
+        const uint32_t slot = slot0 + ((uint32_t)k ^ ((uint32_t)k >> 1));
         R re[1 << RL], im[1 << RL];
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
-            const cx<R> v = pv[(uint32_t)j << TL];
-            re[j] = ur[j] * v.re + ui[j] * v.im;
-            im[j] = ur[j] * v.im - ui[j] * v.re;
+            re[j] = ur[j] * vr[j] + ui[j] * vi[j];
+            im[j] = ur[j] * vi[j] - ui[j] * vr[j];
         }
         tile_fwht<R, TL, RL, 0>(re, im, lds);
         store_tile<R, TL, RL>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
+        if (k + 1 < fam) {
+            switch (__builtin_ctz((unsigned)(k + 1))) {
+                case 0: regs_lane_xor<0, R, RL>(vr, vi); break;
+                case 1: regs_lane_xor<1, R, RL>(vr, vi); break;
+                case 2: regs_lane_xor<2, R, RL>(vr, vi); break;
+                default: regs_lane_xor<3, R, RL>(vr, vi); break;
+            }
+        }
     }
 }
 

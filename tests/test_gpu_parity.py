@@ -147,6 +147,40 @@ def test_T_on_stabilizer_product_closed_form():
     assert abs(g["nullity"] - n_xy) < 1e-12
 
 
+@pytest.mark.parametrize("dtype,batch", [(1, 256), (1, 16), (0, 256)])
+def test_exact_shared_runs_closed_form(dtype, batch):
+    # N = 20 sweeps share the state tiles over runs of 16 (batch 256) or 2 (batch 16)
+    # consecutive families; the closed form of T|stabilizer product> must hold for both
+    n = 20
+    labels = synth.stabilizer_product_spec(n, 23)
+    psi = synth.states.stabilizer_product(labels, t_on=set(range(n)))
+    n_xy = sum(lab[0] != "z" for lab in labels)
+    log("shared-run sweep n=%d dtype=%d batch=%d" % (n, dtype, batch))
+    ctx = make_ctx(as_input(psi, dtype), dtype, x_batch=batch)
+    g = ctx.exact(1e-7 if dtype == 0 else 1e-4)
+    ctx.close()
+    tol = 1e-9 if dtype == 0 else 2e-4
+    assert abs(g["M"][0] - n_xy * math.log2(4 / 3)) < tol * n
+    assert abs(g["M1"] - 0.5 * n_xy) < tol * n
+    assert abs(g["nullity"] - n_xy) < 1e-12
+    assert g["n_samples"] == 1 << n
+
+
+def test_exact_sums_do_not_depend_on_run_length():
+    # the per-family values and the fixed-order sweep sum are independent of how
+    # the first pass groups families: batch 256 (runs of 16) and 16 (runs of 2)
+    n = 20
+    psi = synth.haar_state(n, 2020).astype(np.complex64)
+    out = []
+    for batch in (256, 16):
+        log("run-length independence n=%d batch=%d" % (n, batch))
+        ctx = make_ctx(psi, pw.PW_C64, x_batch=batch)
+        out.append(ctx.exact(1e-4))
+        ctx.close()
+    import json
+    assert json.dumps(out[0], sort_keys=True) == json.dumps(out[1], sort_keys=True)
+
+
 @pytest.mark.parametrize("n,dtype", [(14, 0), (15, 1), (16, 0)])
 def test_signed_family_values(n, dtype):
     psi = as_input(synth.haar_state(n, 500 + n), dtype)
