@@ -57,10 +57,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, dtype_tag):
-    """HBM traffic per launch from the committed rocprofv3 --pmc summary, if it was
+def load_traffic(kernel, summary="pmc_traffic_c64_n20.json"):
+    """HBM traffic per launch from a committed rocprofv3 --pmc summary, if it was
     taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_%s_n20.json" % dtype_tag)
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -151,6 +151,10 @@ def mc_leg(pw, torch, stream, eta, timing_every):
     # algorithmic traffic; the path time per family is the sum of the kernel averages.
     per_fam_us = sum(v["avg_us"] / v["families_per_launch"] for v in kt.values())
     alg = float(1 << n) * 8.0
+    # counter-measured bytes per family of the two kernels (first pass, reducing column pass)
+    t_first = load_traffic("k_first", "pmc_traffic_c64_n28_mc.json")
+    t_col = load_traffic("k_column", "pmc_traffic_c64_n28_mc.json")
+    traffic = t_first + t_col if t_first is not None and t_col is not None else None
     return {"workload": "N=%d T-doped Clifford state, eta=%d, N_T=%d, complex64; Clifford preconditioning %d "
                         "brick-wall layers; x ~ exact marginal (x != 0) plus x = 0, %d per batch; stop at "
                         "std-err(M_2) <= %g or %d families" % (n, eta, 2 * n, 2 * n, MC_BATCH, MC_TARGET_SE, MC_MAX),
@@ -161,7 +165,9 @@ def mc_leg(pw, torch, stream, eta, timing_every):
             "kernels": kt,
             "roofline": {"bound": "hbm", "achieved": round(alg / (per_fam_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(alg / (per_fam_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                         "note": "one read of psi per family over the summed kernel time of the path"}}
+                         "traffic": traffic,
+                         "note": "one read of psi per family over the summed kernel time of the path; traffic = "
+                                 "rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per family of the first and reducing passes"}}
 
 
 def main():
@@ -252,7 +258,7 @@ def main():
     achieved = alg_ops / (d["avg_ms"] * 1e-3) / 1e9
     path_us = sum(v["avg_ms"] * 1e3 / v["families_per_launch"] for v in kt64.values())
     alg_bytes_family = float(1 << n) * 8.0       # one read of psi per family (complex64)
-    traffic = load_traffic(KNAME[dom], "c64")
+    traffic = load_traffic(KNAME[dom])
     roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
                 "frac": round(achieved / VALU_PEAK_GOPS, 4),
                 "traffic": traffic, "kernel": KCLASS[dom],

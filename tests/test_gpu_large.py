@@ -1,10 +1,11 @@
-"""Full-size checks (N = 26, 28, 30) through the C ABI.
+"""Full-size checks (N = 23..30) through the C ABI.
 
 At these sizes the oracle cannot enumerate, so the checks use (a) the paper's
-closed forms for the product magic state |psi_m> = |T>^{N/2} |0>^{N/2}
-(Supplemental Material, Eq. sm-psi-m-m2x: m_{2;x} = 2^{-3N/2-k} when x_B = 0 and
-|x_A| = k, else 0), with p(x) = 2^{-N/2} [x_B = 0] (product of one-qubit marginals:
-1/2, 1/2 for |T>, 1, 0 for |0>) and nu_x = 2^{N/2} for x = 0, else 0;
+closed forms for the product magic state |psi_m> = |T>^h |0>^{N-h}, h = floor(N/2)
+(Supplemental Material, Eq. sm-psi-m-m2x for even N: m_{2;x} = 2^{-3N/2-k} when
+x_B = 0 and |x_A| = k, else 0; the same product argument gives 2^{-(N+h)-k} for
+odd N), with p(x) = 2^{-h} [x_B = 0] (product of one-qubit marginals: 1/2, 1/2 for
+|T>, 1, 0 for |0>) and nu_x = 2^{N-h} for x = 0, else 0;
 (b) Clifford invariance of M_2 (Clifford preconditioning section) through the
 Monte Carlo estimator at N = 28; (c) per-family oracle values on sampled x for a
 Haar state at N = 26.
@@ -40,9 +41,10 @@ def psi_m_checks(n, g, xs):
         x = int(x)
         xa, xb = x & ((1 << h) - 1), x >> h
         k = bin(xa).count("1")
-        m2 = 0.0 if xb else 2.0 ** (-1.5 * n - k)
+        # per qubit, sum_z |<P>|^4 is 2 for |0> (x_q = 0), 1 or 1/2 for |T> (x_q = 0, 1)
+        m2 = 0.0 if xb else 2.0 ** (-(n + h) - k)
         p = 0.0 if xb else 2.0 ** (-h)
-        scale = 2.0 ** (-1.5 * n)
+        scale = 2.0 ** (-(n + h))
         assert abs(g["m"][i, 0] - m2) <= 2e-5 * max(m2, scale * 2.0 ** (-h)), (n, x, g["m"][i, 0], m2)
         assert abs(g["p"][i] - p) <= 2e-5 * 2.0 ** (-h), (n, x, g["p"][i], p)
         assert int(g["nu"][i]) == ((1 << (n - h)) if x == 0 else 0), (n, x, g["nu"][i])
@@ -55,7 +57,7 @@ def _xs_for(n, seed):
     return np.array(sorted(set(lst)), dtype=np.uint64)
 
 
-@pytest.mark.parametrize("n", [28, 30])
+@pytest.mark.parametrize("n", [23, 24, 25, 27, 28, 30])
 def test_psi_m_closed_forms_full_size(n):
     psi = psi_m_sparse(n)
     xs = _xs_for(n, 1000 + n)
