@@ -166,6 +166,7 @@ def mc_leg(pw, torch, stream, eta, timing_every):
             "roofline": {"bound": "hbm", "achieved": round(alg / (per_fam_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(alg / (per_fam_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                          "traffic": traffic,
+                         "traffic_GBps": round(traffic / (per_fam_us * 1e-6) / 1e9, 1) if traffic else None,
                          "note": "one read of psi per family over the summed kernel time of the path; traffic = "
                                  "rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per family of the first and reducing passes"}}
 
@@ -247,9 +248,11 @@ def main():
     strings = float(1 << n) ** 2
     value = args.steps * strings / el64
 
-    # dominant kernel = largest share of the sampled time per family.  At N = 20 the state
-    # (8 MiB) and the batch's half spectra (256 MiB) stay in L2/MALL, so the roof that binds
-    # is VALU issue, not HBM: achieved = algorithmic VALU operations per launch / duration.
+    # dominant kernel = largest share of the sampled time per family.  The algorithmic
+    # bytes of the path are one read of the 8 MiB state per family (served from L2/MALL at
+    # N = 20), far below what the arithmetic needs, so the roof is VALU issue: achieved =
+    # algorithmic VALU operations per launch / duration.  The counter traffic of the same
+    # kernel (the half spectra it writes) is reported beside it as a rate.
     dom = max(kt64, key=lambda k: kt64[k]["avg_ms"] / kt64[k]["families_per_launch"])
     d = kt64[dom]
     half_points = float(1 << (n - 1))
@@ -269,8 +272,11 @@ def main():
                 "path_us_per_family": round(path_us, 4),
                 "hbm_equivalent": {"algorithmic_bytes_per_family": alg_bytes_family,
                                    "GBps": round(alg_bytes_family / (path_us * 1e-6) / 1e9, 1),
-                                   "note": "one read of psi per family over the whole path time; psi and the "
-                                           "intermediates are served from L2/MALL at this size"}}
+                                   "note": "one read of psi per family over the whole path time"}}
+    if traffic is not None:
+        roofline["traffic_GBps"] = round(traffic / (d["avg_ms"] * 1e-3) / 1e9, 1)
+        roofline["traffic_note"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch (L2 <-> fabric: MALL or HBM) "
+                                    "over the HIP-event duration")
 
     el128 = r128 = None
     if args.steps_c128 > 0:
