@@ -171,6 +171,68 @@ def mc_leg(pw, torch, stream, eta, timing_every):
                                  "rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per family of the first and reducing passes"}}
 
 
+LEARNED_N = 30
+
+
+def learned_leg(pw, torch, stream, kind, draws, pilot):
+    """Learned (MADE) proposal against the plain exact-marginal sampler at N = 30, complex64,
+    the same number of draws each (x = 0 evaluated in both).  kind "psi_m": |T>^15 |0>^15
+    (exact M_2 = 15 log2(4/3)); kind "tdoped": |0...0> through a T-doped brick-wall stream
+    (eta = 8, N_T = 60).  The learned run trains a 30 -> 256 -> 256 -> 30 MADE on `pilot`
+    exact-marginal draws (weights m_2/p) and samples the defensive mixture with lambda = 0.1.
+    Reported: M_2 +- sigma, draws, wall times, and the draws sigma = 1e-3 would need
+    (n sigma^2 / 1e-6) for each."""
+    import numpy as np
+    import synth
+    n = LEARNED_N
+    seed = synth.SEED_BASE + 5 + (0 if kind == "psi_m" else 100)
+    dev = "cuda:0"
+    psi = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
+    exact = None
+    if kind == "psi_m":
+        h = n // 2
+        b = np.arange(1 << h)
+        pc = np.array([bin(int(v)).count("1") for v in b])
+        amp = (2.0 ** (-h / 2)) * np.exp(1j * np.pi / 4 * pc)
+        psi[: 1 << h] = torch.from_numpy(amp.astype(np.complex64)).to(dev)
+        exact = h * math.log2(4 / 3)
+    else:
+        psi[0] = 1.0
+    ctx = pw.Context(0, stream)
+    ctx.bind(psi, pw.PW_C64)
+    pw.pw_set_moments(ctx.h, 2)
+    if kind != "psi_m":
+        ctx.apply_gates(*synth.gates_to_arrays(synth.tdoped_stream(n, 8, 2 * n, seed)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 64, draws + 1, 0.0, seed + 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hidden = 256
+    pw.pw_made_init(ctx.h, n, hidden, synth.made_init(n, hidden, seed + 2))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    learned = pw.pw_mc_learned(ctx.h, 1e-4, 64, draws + 1, 0.0, seed + 3, 0.1, pilot, 20, 128, 3e-3)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ctx.close()
+    del psi
+
+    def leg(r, wall):
+        se = r["M_se"][0]
+        need = r["n_samples"] * (se / 1e-3) ** 2
+        return {"M2": r["M"][0], "M2_se": se, "r2": r["r"][0], "n_samples": r["n_samples"], "wall_s": wall,
+                "samples_for_se_1e-3": need}
+    out = {"workload": ("N=30 psi_m = |T>^15 |0>^15, complex64" if kind == "psi_m" else
+                        "N=30 T-doped Clifford state, eta=8, N_T=60, complex64, no preconditioning"),
+           "draws_each": draws, "plain_marginal": leg(plain, t1 - t0),
+           "learned": dict(leg(learned, t3 - t2), pilot=pilot, hidden=hidden, lam=0.1, epochs=20, minibatch=128,
+                           lr=3e-3, note="wall time includes the pilot draws and the training")}
+    if exact is not None:
+        out["M2_exact"] = exact
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +247,10 @@ def main():
                     help="scrambling ratios of the N=28 Monte Carlo leg (the workload lists 1, 4 and 16)")
     ap.add_argument("--batch", type=int, default=0,
                     help="families per launch (0: the library default for the state size)")
+    ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=None,
+                    help="also run the N=30 learned-vs-plain proposal comparison (minutes; off by default)")
+    ap.add_argument("--learned-draws", type=int, default=2048)
+    ap.add_argument("--learned-pilot", type=int, default=4096)
     ap.add_argument("--max-alpha", type=int, default=2, choices=(2, 4),
                     help="moments computed per family (the workload asks for M_1, M_2 and the nullity)")
     args = ap.parse_args()
@@ -310,6 +376,10 @@ def main():
                        "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0]}
     if not args.no_mc_leg:
         out["m2_wall_time"] = [mc_leg(pw, torch, stream, eta, args.timing_every) for eta in args.mc_eta]
+    if args.learned_leg is not None:
+        kinds = args.learned_leg or ["psi_m", "tdoped"]
+        out["learned_vs_plain"] = [learned_leg(pw, torch, stream, k, args.learned_draws, args.learned_pilot)
+                                   for k in kinds]
     if not args.no_cpu_baseline:
         import oracle
         psi_host = psi128_dev.cpu().numpy()
