@@ -99,7 +99,10 @@ typedef struct {
     double nullity;    /* N - log2 nu_cnt (pw_exact only; NaN for pw_mc)               */
     uint64_t nu_cnt;   /* sum_x nu(x) (pw_exact only)                                  */
     uint64_t n_samples;/* families evaluated, x = 0 included                           */
-    double r[3];       /* sample sd of the per-family terms / their mean (pw_mc)       */
+    double r[3];       /* pw_mc: sample sd of the per-draw terms / their mean;          *
+                        * pw_exact: r_alpha = Std_{x!=0}(m_{alpha;x}) / E_x[m_{alpha;x}]  *
+                        * (Supplemental, brick-wall circuits: the spread that sets the    *
+                        * Monte Carlo sample count)                                       */
     double gap;        /* max over families of gap                                     */
 } pw_result;
 

@@ -642,7 +642,12 @@ pw_status pw_exact(pw_ctx c, double eps, pw_result* out) {
         r.S_se[a] = 0.0;
         r.M[a] = log2(h.S[a]) / (1.0 - (a + 2)) - n;
         r.M_se[a] = 0.0;
-        r.r[a] = NAN;
+        // r_alpha = Std_{x != 0}(m_{alpha;x}) / E_x[m_{alpha;x}] (population spread over
+        // the d - 1 families x != 0, mean over all d families)
+        const double dm1 = (double)(d - 1);
+        const double mean_nz = h.Snz[a] / dm1;
+        const double var = fmax(h.Q[a] / dm1 - mean_nz * mean_nz, 0.0);
+        r.r[a] = d > 1 ? sqrt(var) / (h.S[a] / (double)d) : NAN;
     }
     r.L = h.L;
     r.L_se = 0.0;

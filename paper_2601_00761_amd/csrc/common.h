@@ -33,8 +33,11 @@ struct SweepSums {
     double gap;
     uint64_t nu_cnt;
     uint64_t count;
+    double Snz[3];  // sum over x != 0 of m_{alpha;x}
+    double Q[3];    // sum over x != 0 of m_{alpha;x}^2 (spread of the family values)
+    double pad[2];
 };
-static_assert(sizeof(SweepSums) == 64, "SweepSums layout");
+static_assert(sizeof(SweepSums) == 128, "SweepSums layout");
 
 // The pass schedule of one transform of 2^nh points (nh = n - 1 after the
 // Hermitian halving): a first tile pass over bits [0, k1) that also forms the

@@ -769,6 +769,8 @@ __device__ __forceinline__ void zero_sums(SweepSums& t) {
     t.gap = -1.0;
     t.nu_cnt = 0;
     t.count = 0;
+    for (int a = 0; a < 3; ++a) t.Snz[a] = t.Q[a] = 0.0;
+    t.pad[0] = t.pad[1] = 0.0;
 }
 
 __device__ __forceinline__ void add_sums(SweepSums& a, const SweepSums& b) {
@@ -780,6 +782,10 @@ __device__ __forceinline__ void add_sums(SweepSums& a, const SweepSums& b) {
     a.gap = fmax(a.gap, b.gap);
     a.nu_cnt += b.nu_cnt;
     a.count += b.count;
+    for (int k = 0; k < 3; ++k) {
+        a.Snz[k] += b.Snz[k];
+        a.Q[k] += b.Q[k];
+    }
 }
 
 // Fixed-order sum of count per-family results into one SweepSums.
@@ -799,6 +805,12 @@ k_reduce_fam(const FamilyRes* __restrict__ in, int64_t count, SweepSums* __restr
         t.gap = fmax(t.gap, v.gap);
         t.nu_cnt += v.nu;
         t.count += 1;
+        if (v.x != 0) {
+            for (int a = 0; a < 3; ++a) {
+                t.Snz[a] += v.m[a];
+                t.Q[a] = fma(v.m[a], v.m[a], t.Q[a]);
+            }
+        }
     }
     sh[threadIdx.x] = t;
     __syncthreads();

@@ -1,7 +1,7 @@
 """Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
 
 This package produces *inputs only*: state vectors, random two-qubit Clifford
-gate lists and T-gate positions.  It holds none of the method's arithmetic
+and Haar gate lists and T-gate positions.  It holds none of the method's arithmetic
 (no Pauli expectation values, no transforms, no gate application, no
 sampling of Pauli strings).  Both the CPU oracle and the HIP library consume
 what it produces, each with its own code.
@@ -20,7 +20,8 @@ from .states import (haar_state, psi_m_state, product_state, stabilizer_product_
                      T_STATE, SIX_STABILIZER_STATES)
 from .clifford import clifford2_table, CLIFFORD2_ORDER
 from .circuits import (Gate, brickwall_pairs, random_brickwall_clifford, tdoped_stream,
-                       gates_to_arrays, t_gate, GATE_2Q, GATE_1Q_DIAG)
+                       gates_to_arrays, t_gate, GATE_2Q, GATE_1Q_DIAG, haar_u4, open_pairs,
+                       random_brickwall_haar, haar_doped_stream)
 from .made_init import made_init, made_sizes, made_param_count
 
 __all__ = [
@@ -30,6 +31,7 @@ __all__ = [
     "clifford2_table", "CLIFFORD2_ORDER",
     "Gate", "brickwall_pairs", "random_brickwall_clifford", "tdoped_stream",
     "gates_to_arrays", "t_gate", "GATE_2Q", "GATE_1Q_DIAG",
+    "haar_u4", "open_pairs", "random_brickwall_haar", "haar_doped_stream",
     "made_init", "made_sizes", "made_param_count",
     "SEED_BASE",
 ]

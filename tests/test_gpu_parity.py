@@ -101,11 +101,14 @@ def test_exact_enumeration_haar(n, dtype):
     eps = 1e-7 if dtype == pw.PW_C128 else 1e-4
     g = ctx.exact(eps)
     ctx.close()
-    r = oracle.alg1(psi, eps=eps, max_alpha=4)
+    r = oracle.alg1(psi, eps=eps, max_alpha=4, per_x=True)
     tol = REL64 if dtype == pw.PW_C128 else 2e-5
     for a in range(3):
         assert abs(g["S"][a] / r["S"][a] - 1) <= tol
         assert abs(g["M"][a] - r["M"][a + 2]) <= tol * max(1.0, abs(r["M"][a + 2])) * 10
+        # r_alpha: population spread over x != 0 over the mean over all x
+        m = r["per_x"]["m"][:, a]
+        assert abs(g["r"][a] / (np.std(m[1:]) / m.mean()) - 1) <= tol * 1e3
     assert abs(g["M1"] - r["M1"]) <= tol * max(1, abs(r["M1"])) * 10
     assert g["nu_cnt"] == r["nu_cnt"]
     assert abs(g["P"] - 1) <= (1e-12 if dtype == pw.PW_C128 else 1e-5)
@@ -131,6 +134,19 @@ def test_stabilizer_state_prepared_on_gpu(n, dtype):
     for a in range(3):
         assert abs(g["M"][a]) <= (1e-10 if dtype == 0 else 1e-4)
     assert g["nu_cnt"] == 1 << n and g["nullity"] == 0.0
+
+
+@pytest.mark.parametrize("n,dtype", [(12, 0), (16, 0), (14, 1)])
+def test_exact_r2_of_psi_m_closed_form(n, dtype):
+    # Supplemental Material, Eq. sm-psi-m-ratio-exact
+    psi = synth.psi_m_state(n)
+    log("psi_m r2 n=%d dtype=%d" % (n, dtype))
+    ctx = make_ctx(as_input(psi, dtype), dtype)
+    g = ctx.exact(1e-7 if dtype == 0 else 1e-4)
+    ctx.close()
+    h = n / 2
+    ref = (8 / 3) ** h * math.sqrt(((5 / 4) ** h - 1) / (4 ** h - 1) - ((1.5 ** h - 1) ** 2) / (4 ** h - 1) ** 2)
+    assert abs(g["r"][0] / ref - 1) < (1e-9 if dtype == 0 else 1e-4)
 
 
 def test_T_on_stabilizer_product_closed_form():

@@ -336,3 +336,42 @@ def test_mixed_product_and_maximally_entangled():
         psi[a + (a << 3)] = 1 / math.sqrt(8)
     r = oracle.mixed(psi, 3)
     assert abs(r["S2"] - 3) < 1e-12 and abs(r["M"][2]) < 1e-12
+
+
+def test_haar_two_qubit_gates_have_haar_moments():
+    # input check of the Haar generator: unitary, E|U_00|^2 = 1/4, E|U_00|^4 = 2/(4*5)
+    us = np.array([synth.haar_u4(991, k) for k in range(4000)])
+    assert np.max(np.abs(np.einsum("kji,kjl->kil", us.conj(), us) - np.eye(4))) < 1e-12
+    a2 = np.abs(us[:, 0, 0]) ** 2
+    assert abs(a2.mean() - 0.25) < 4.5 * a2.std() / math.sqrt(len(a2))
+    a4 = a2 ** 2
+    assert abs(a4.mean() - 0.1) < 4.5 * a4.std() / math.sqrt(len(a4))
+
+
+def _mean_w(states):
+    # w = 2^{-M_2} = sum_P c_P^4 / d per state, from the oracle's Algorithm 1
+    w = np.array([2.0 ** (-oracle.alg1(psi, max_alpha=2)["M"][2]) for psi in states])
+    return w.mean(), w.std() / math.sqrt(len(w))
+
+
+def _run(n, gates):
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1
+    return oracle.apply_gates(psi, *synth.gates_to_arrays(gates))
+
+
+def test_two_qubit_haar_layer_average_magic():
+    # End Matter, two-qubit Haar doping with N_C = 0: independent Haar states on the pairs
+    # (0,1), (2,3); 2^{-M_2} factorises over the pairs and each factor averages to
+    # 1 - M_lin^Haar = 4/(d+3) = 4/7 for d = 4, so E[2^{-M_2}] = (4/7)^2
+    states = [_run(4, synth.haar_doped_stream(4, 0, 1, 5000 + r)) for r in range(600)]
+    m, se = _mean_w(states)
+    assert abs(m - (4 / 7) ** 2) < 4.5 * se
+
+
+def test_deep_haar_brickwall_reaches_the_haar_average():
+    # a deep brick-wall of Haar gates on N = 4 is a 2-design to high accuracy:
+    # E[2^{-M_2}] = 4/(2^N+3) (Supplemental, M_lin of Haar states)
+    states = [_run(4, synth.random_brickwall_haar(4, 16, 7000 + r)) for r in range(600)]
+    m, se = _mean_w(states)
+    assert abs(m - 4 / 19) < 4.5 * se
