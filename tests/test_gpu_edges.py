@@ -1,0 +1,106 @@
+"""Edge cases through the C ABI: empty lists, the smallest states, computational basis
+states (degenerate marginal), eps = 0, and error paths that must not launch work."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import as_input, log, make_ctx
+
+pytestmark = pytest.mark.gpu
+pw = pytest.importorskip("paper_2601_00761_amd")
+
+
+def test_empty_family_lists():
+    psi = synth.haar_state(12, 3)
+    ctx = make_ctx(psi, pw.PW_C128)
+    log("empty lists")
+    out = ctx.eval_x(np.zeros(0, dtype=np.uint64), 1e-7)
+    assert len(out) == 0
+    import torch
+    d_out = torch.empty(64, dtype=torch.uint8, device="cuda:0")
+    pw.pw_eval_x_device(ctx.h, None, 0, 1e-7, d_out)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_exact_smallest_states(n, dtype):
+    psi = as_input(synth.haar_state(n, 40 + n), dtype)
+    log("exact smallest n=%d dtype=%d" % (n, dtype))
+    ctx = make_ctx(psi, dtype)
+    g = ctx.exact(1e-7 if dtype == 0 else 1e-4)
+    ctx.close()
+    r = oracle.alg1(psi, eps=1e-7 if dtype == 0 else 1e-4, max_alpha=4)
+    tol = 1e-10 if dtype == 0 else 2e-5
+    for a in range(3):
+        assert abs(g["S"][a] / r["S"][a] - 1) <= tol
+    assert g["nu_cnt"] == r["nu_cnt"] and g["n_samples"] == 1 << n
+
+
+def test_single_qubit_T_state():
+    # one qubit in |T>: M_2 = log2(4/3), M_1 = 1/2 (Bloch vector (1/sqrt2, 1/sqrt2, 0))
+    psi = np.array([1, np.exp(1j * np.pi / 4)], dtype=np.complex128) / math.sqrt(2)
+    ctx = make_ctx(psi, pw.PW_C128)
+    log("single-qubit T")
+    g = ctx.exact(1e-7)
+    ctx.close()
+    assert abs(g["M"][0] - math.log2(4 / 3)) < 1e-12
+    assert abs(g["M1"] - 0.5) < 1e-12
+    assert g["nu_cnt"] == 1 and g["nullity"] == 1.0
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_basis_state_degenerate_marginal(dtype):
+    # |0...0>: every Z string has |c| = 1, every other string 0.  Exact: M = 0,
+    # nu_cnt = 2^N; the x-marginal is a point mass on x = 0, so the marginal sampler
+    # reports PW_ERR_UNSUPPORTED; the uniform estimator returns S = m_{2;0} = d/d^2 exactly.
+    n = 12
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1
+    ctx = make_ctx(psi, dtype)
+    log("basis state dtype=%d" % dtype)
+    g = ctx.exact(1e-7 if dtype == 0 else 1e-4)
+    assert g["M"][0] == 0.0 and g["nu_cnt"] == 1 << n and g["nullity"] == 0.0
+    with pytest.raises(pw.PWError) as e:
+        ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 64, 129, 0.0, 1)
+    assert e.value.status == 8
+    u = ctx.mc(pw.PW_SAMPLER_UNIFORM_NZ, 1e-4, 64, 129, 0.0, 1)
+    ctx.close()
+    assert u["S"][0] == 2.0 ** -n and u["M"][0] == 0.0 and u["S_se"][0] == 0.0
+
+
+def test_eps_zero_counts_only_exact_unit_magnitudes():
+    # with eps = 0 the two-sided test |F|^2 in ((1-eps)^2, (1+eps)^2) is empty
+    n = 10
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1
+    ctx = make_ctx(psi, pw.PW_C128)
+    log("eps zero")
+    xs = np.array([0, 1, 5], dtype=np.uint64)
+    out0 = ctx.eval_x(xs, 0.0)
+    out7 = ctx.eval_x(xs, 1e-7)
+    ctx.close()
+    assert [int(v) for v in out0["nu"]] == [0, 0, 0]
+    assert [int(v) for v in out7["nu"]] == [1 << n, 0, 0]
+
+
+def test_argument_errors_launch_nothing():
+    n = 10
+    ctx = make_ctx(synth.haar_state(n, 9), pw.PW_C128)
+    log("argument errors")
+    for call, status in [(lambda: ctx.eval_x(np.array([0], dtype=np.uint64), 1.0), 1),
+                         (lambda: ctx.eval_x(np.array([0], dtype=np.uint64), -1e-3), 1),
+                         (lambda: ctx.mc(pw.PW_SAMPLER_UNIFORM_NZ, 1e-7, 0, 100, 0.0, 1), 1),
+                         (lambda: ctx.mc(pw.PW_SAMPLER_UNIFORM_NZ, 1e-7, 64, 2, 0.0, 1), 1),
+                         (lambda: ctx.mc(7, 1e-7, 64, 100, 0.0, 1), 1)]:
+        with pytest.raises(pw.PWError) as e:
+            call()
+        assert e.value.status == status
+    # the context still works afterwards
+    g = ctx.exact(1e-7)
+    ctx.close()
+    assert g["n_samples"] == 1 << n
