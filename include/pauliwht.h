@@ -158,7 +158,7 @@ PW_API pw_status pw_eval_x(pw_ctx ctx, const uint64_t* xs, int64_t n_x, double e
 PW_API pw_status pw_eval_x_device(pw_ctx ctx, const uint64_t* d_xs, int64_t n_x, double eps, pw_xres* d_out);
 
 /* The signed expectation values c(x, z) = (-i)^{|x&z|} F_x(z) of one family,
- * z = 0..2^n-1, into the host array c (2^n doubles).  n <= 26. */
+ * z = 0..2^n-1, into the host array c (2^n doubles).  1 <= n <= 26. */
 PW_API pw_status pw_family_values(pw_ctx ctx, uint64_t x, double* c);
 
 /* Draw n x-strings on the device (Philox4x32-10 counters keyed by seed; sample i

@@ -573,12 +573,10 @@ pw_status pw_family_values(pw_ctx c, uint64_t x, double* cvals) {
     if (!cvals) return fail(PW_ERR_ARG, "null output");
     if (c->n > FAMILY_VALUES_MAX_QUBITS) return fail(PW_ERR_RANGE, "family values limited to n <= %d", FAMILY_VALUES_MAX_QUBITS);
     if (x >= (1ull << c->n)) return fail(PW_ERR_RANGE, "x not below 2^n");
-    if (c->n < 14) return fail(PW_ERR_UNSUPPORTED, "family values need n >= 14 (multi-pass transform)");
     const bool dbl = c->dtype == PW_C128;
     void* G = c->ws + c->L.work;
     double* cv = reinterpret_cast<double*>(c->ws + c->L.work + align256(((size_t)1 << (c->n - 1)) * esize(c->dtype)));
     Plan P = make_plan(c->n, dbl);
-    if (P.fused) return fail(PW_ERR_UNSUPPORTED, "family values need the multi-pass transform");
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
     PW_HIP(transform_one(P, dbl, c->psi, x, G, c->stream));
     PW_HIP(signed_values(P, dbl, G, x, cv, c->stream));

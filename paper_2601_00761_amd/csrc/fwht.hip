@@ -583,6 +583,18 @@ __device__ __forceinline__ void store_tile(cx<R>* __restrict__ dst, const R (&re
     for (int j = 0; j < (1 << RL); ++j) st_point<STREAM>(p + ((uint32_t)j << A), re[j], im[j]);
 }
 
+// Half spectrum G of one family written out (signed values of small states).
+template <typename R, int TL, int RL>
+__global__ void __launch_bounds__(1 << TL)
+k_fused_store(const cx<R>* __restrict__ psi, int n, uint64_t x, cx<R>* __restrict__ G) {
+    constexpr int K = TL + RL;
+    __shared__ cx<R> lds[Lds<K>::elems];
+    R re[1 << RL], im[1 << RL];
+    load_products<R, TL, RL>(psi, n - 1, (uint32_t)x, 0u, re, im);
+    tile_fwht<R, TL, RL, 0>(re, im, lds);
+    store_tile<R, TL, RL>(G, re, im);
+}
+
 // First pass of a multi-pass transform: products + low K index bits of one tile.
 // Grid: (tiles per family, families).
 template <typename R, int TL, int RL, bool SPLIT = false>
@@ -1021,11 +1033,34 @@ first_done:
     return hipGetLastError();
 }
 
+template <typename R, int K>
+hipError_t launch_store_k(const void* psi, int n, uint64_t x, void* G, hipStream_t st) {
+    constexpr int RL0 = K < 4 ? K : 4;
+    constexpr int TL = K == 13 ? 9 : K - RL0;
+    constexpr int RL = K - TL;
+    hipLaunchKernelGGL((k_fused_store<R, TL, RL>), dim3(1), dim3(1 << TL), 0, st, (const cx<R>*)psi, n, x, (cx<R>*)G);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* work, hipStream_t st) {
-    // the multi-pass schedule without the final reduction
     const int nh = P.nh;
-    if (P.fused || nh <= K_FIRST) return hipErrorInvalidValue;
+    if (P.fused) {
+        // the single-workgroup transform, written out instead of reduced
+        switch (nh) {
+#define PW_CASE(K) \
+    case K: return launch_store_k<R, K>(psi, P.n, x, work, st);
+            PW_CASE(0) PW_CASE(1) PW_CASE(2) PW_CASE(3) PW_CASE(4) PW_CASE(5) PW_CASE(6)
+            PW_CASE(7) PW_CASE(8) PW_CASE(9) PW_CASE(10) PW_CASE(11) PW_CASE(12)
+#undef PW_CASE
+            case 13:
+                if constexpr (sizeof(R) == 4) return launch_store_k<R, 13>(psi, P.n, x, work, st);
+                return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    // the multi-pass schedule without the final reduction
+    if (nh <= K_FIRST) return hipErrorInvalidValue;
     bool done = false;
     if constexpr (sizeof(R) == 4) {
         if (P.k1 == 15) {

@@ -197,11 +197,11 @@ def test_exact_sums_do_not_depend_on_run_length():
     assert json.dumps(out[0], sort_keys=True) == json.dumps(out[1], sort_keys=True)
 
 
-@pytest.mark.parametrize("n,dtype", [(14, 0), (15, 1), (16, 0)])
+@pytest.mark.parametrize("n,dtype", [(1, 0), (2, 1), (5, 0), (10, 1), (13, 0), (14, 1), (14, 0), (15, 1), (16, 0)])
 def test_signed_family_values(n, dtype):
     psi = as_input(synth.haar_state(n, 500 + n), dtype)
     ctx = make_ctx(psi, dtype)
-    for x in [0, 1, 6, (1 << n) - 1, 12345 % (1 << n)]:
+    for x in sorted({0, 1, 6 % (1 << n), (1 << n) - 1, 12345 % (1 << n)}):
         log("family values n=%d dtype=%d x=%d" % (n, dtype, x))
         c = ctx.family_values(x)
         F = oracle.spectrum(psi, x)
