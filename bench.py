@@ -123,7 +123,6 @@ def mc_leg(pw, torch, stream, eta, timing_every):
     n = MC_N
     seed = synth.SEED_BASE + 3 + 100 * eta
     kinds, qubits, mats = synth.gates_to_arrays(synth.tdoped_stream(n, eta, 2 * n, seed))
-    pk, pq, pm = synth.gates_to_arrays(synth.random_brickwall_clifford(n, 2 * n, seed + 1))
     psi0 = np.zeros(1 << n, dtype=np.complex64)
     psi0[0] = 1.0
     ctx = pw.Context(0, stream)
@@ -135,7 +134,7 @@ def mc_leg(pw, torch, stream, eta, timing_every):
     pw.pw_timing_enable(ctx.h, 1)
     pw.pw_timing_reset(ctx.h)
     t0 = time.perf_counter()
-    ctx.apply_gates(pk, pq, pm)
+    ctx.precondition(2 * n, seed + 1)
     t1 = time.perf_counter()
     res = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, MC_BATCH, MC_MAX + 1, MC_TARGET_SE, seed + 2)
     torch.cuda.synchronize()

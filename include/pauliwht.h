@@ -148,6 +148,30 @@ PW_API pw_status pw_state_upload(pw_ctx ctx, int n_qubits, pw_dtype dtype, const
  * Host arrays, copied before the call returns.  The state is not re-normalised. */
 PW_API pw_status pw_apply_gates(pw_ctx ctx, int n_gates, const int* kinds, const int* qubits, const double* mats);
 
+/* Clifford preconditioning (Clifford preconditioning section): n_layers brick-wall
+ * layers of two-qubit Cliffords, each drawn uniformly from the 11520-element
+ * two-qubit Clifford group modulo phase, applied in place to the bound state.  Layer
+ * l acts on the pairs (i, i+1) for i = l mod 2, l mod 2 + 2, ...; periodic for even n
+ * (odd layers include (n-1, 0), every layer has n/2 gates), open for odd n.  Gate g
+ * takes the group element floor(W 11520 / 2^64), W the first 64-bit word of
+ * Philox4x32-10 with counter (g, 0, "CLIF") and key seed.  M_alpha and the nullity
+ * are unchanged; the exact marginal changes (the paper uses n_layers = 2n).
+ * Errors: PW_ERR_NO_STATE, PW_ERR_RANGE (n < 2), PW_ERR_ARG (n_layers < 0). */
+PW_API pw_status pw_precondition(pw_ctx ctx, int n_layers, uint64_t seed);
+
+/* The gate list pw_precondition applies for (n, n_layers, seed): *n_gates gates,
+ * pairs qubits[2g], qubits[2g+1] and 4x4 matrices mats[32g ..] (interleaved complex,
+ * row-major, local index b_{q0} + 2 b_{q1}).  Host arrays of the caller; null arrays
+ * are skipped (call once with nulls for the count).  No GPU needed. */
+PW_API pw_status pw_precondition_circuit(int n, int n_layers, uint64_t seed, int64_t* n_gates, int* qubits,
+                                         double* mats);
+
+/* The two-qubit Clifford group modulo phase as the library enumerates it (breadth-first
+ * from the identity over H, S on either qubit and CNOT either way; each element scaled
+ * so that its first nonzero entry is real positive): *count = 11520 matrices into
+ * mats[32 i ..] when mats is not null.  No GPU needed. */
+PW_API pw_status pw_clifford2_table(int* count, double* mats);
+
 /* Evaluate the families of the host list xs[0..n_x) (any x < 2^n, repeats
  * allowed) and write one pw_xres per x to the host array out.  eps is the
  * nullity tolerance (the paper suggests 1e-7 in FP64; use >= 1e-4 with PW_C64). */

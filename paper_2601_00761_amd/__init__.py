@@ -19,7 +19,8 @@ import torch  # noqa: F401,E402
 __all__ = [
     "PWError", "PW_C128", "PW_C64", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
-    "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
+    "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
+    "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
     "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
@@ -105,6 +106,9 @@ def _load():
         "pw_state_bind": ([_vp, _int, _int, _vp, ctypes.POINTER(_dbl)], _int),
         "pw_state_upload": ([_vp, _int, _int, _vp, _vp, ctypes.POINTER(_dbl)], _int),
         "pw_apply_gates": ([_vp, _int, _vp, _vp, _vp], _int),
+        "pw_precondition": ([_vp, _int, _u64], _int),
+        "pw_precondition_circuit": ([_int, _int, _u64, ctypes.POINTER(_i64), _vp, _vp], _int),
+        "pw_clifford2_table": ([ctypes.POINTER(_int), _vp], _int),
         "pw_eval_x": ([_vp, _vp, _i64, _dbl, _vp], _int),
         "pw_eval_x_device": ([_vp, _vp, _i64, _dbl, _vp], _int),
         "pw_family_values": ([_vp, _u64, _vp], _int),
@@ -211,6 +215,29 @@ def pw_apply_gates(ctx, kinds, qubits, mats):
     if mats.size != 16 * len(kinds) or qubits.size != 2 * len(kinds):
         raise ValueError("gate arrays: kinds[g], qubits[g, 2], mats[g, 4, 4]")
     _check(_L.pw_apply_gates(ctx, len(kinds), kinds.ctypes.data, qubits.ctypes.data, mats.ctypes.data))
+
+
+def pw_precondition(ctx, n_layers, seed):
+    _check(_L.pw_precondition(ctx, int(n_layers), int(seed)))
+
+
+def pw_precondition_circuit(n, n_layers, seed):
+    """(qubits int32[g, 2], mats complex128[g, 4, 4]) of the preconditioning circuit."""
+    ng = _i64()
+    _check(_L.pw_precondition_circuit(int(n), int(n_layers), int(seed), ctypes.byref(ng), None, None))
+    q = np.zeros((ng.value, 2), dtype=np.int32)
+    m = np.zeros((ng.value, 4, 4), dtype=np.complex128)
+    _check(_L.pw_precondition_circuit(int(n), int(n_layers), int(seed), ctypes.byref(ng), q.ctypes.data,
+                                      m.ctypes.data))
+    return q, m
+
+
+def pw_clifford2_table():
+    cnt = _int()
+    _check(_L.pw_clifford2_table(ctypes.byref(cnt), None))
+    m = np.zeros((cnt.value, 4, 4), dtype=np.complex128)
+    _check(_L.pw_clifford2_table(ctypes.byref(cnt), m.ctypes.data))
+    return m
 
 
 def pw_eval_x(ctx, xs, eps):
@@ -416,6 +443,9 @@ class Context:
 
     def apply_gates(self, kinds, qubits, mats):
         pw_apply_gates(self.h, kinds, qubits, mats)
+
+    def precondition(self, n_layers, seed):
+        pw_precondition(self.h, n_layers, seed)
 
     def eval_x(self, xs, eps):
         return pw_eval_x(self.h, xs, eps)

@@ -542,6 +542,49 @@ pw_status pw_apply_gates(pw_ctx c, int ng, const int* kinds, const int* qubits, 
     return PW_OK;
 }
 
+pw_status pw_clifford2_table(int* count, double* mats) {
+    const int m = clifford2_count();
+    if (count) *count = m;
+    if (mats)
+        for (int i = 0; i < m; ++i) clifford2_matrix(i, mats + 32 * (size_t)i);
+    return PW_OK;
+}
+
+pw_status pw_precondition_circuit(int n, int n_layers, uint64_t seed, int64_t* n_gates, int* qubits, double* mats) {
+    if (n < 2 || n > MAX_QUBITS) return fail(PW_ERR_RANGE, "n=%d outside [2, %d]", n, MAX_QUBITS);
+    if (n_layers < 0) return fail(PW_ERR_ARG, "negative layer count");
+    std::vector<int> q, idx;
+    brickwall_clifford(n, n_layers, seed, q, idx);
+    if (n_gates) *n_gates = (int64_t)idx.size();
+    for (size_t g = 0; g < idx.size(); ++g) {
+        if (qubits) {
+            qubits[2 * g] = q[2 * g];
+            qubits[2 * g + 1] = q[2 * g + 1];
+        }
+        if (mats) clifford2_matrix(idx[g], mats + 32 * g);
+    }
+    return PW_OK;
+}
+
+pw_status pw_precondition(pw_ctx c, int n_layers, uint64_t seed) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (c->n < 2) return fail(PW_ERR_RANGE, "preconditioning needs n >= 2");
+    if (n_layers < 0) return fail(PW_ERR_ARG, "negative layer count");
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    std::vector<int> q, idx;
+    brickwall_clifford(c->n, n_layers, seed, q, idx);
+    const bool dbl = c->dtype == PW_C128;
+    double m32[32];
+    for (size_t g = 0; g < idx.size(); ++g) {
+        clifford2_matrix(idx[g], m32);
+        PW_HIP(apply_gate2(dbl, c->psi, c->n, q[2 * g], q[2 * g + 1], m32, c->stream));
+    }
+    c->cdf_valid = false;
+    PW_HIP(hipStreamSynchronize(c->stream));
+    return PW_OK;
+}
+
 pw_status pw_eval_x(pw_ctx c, const uint64_t* xs, int64_t nx, double eps, pw_xres* out) {
     pw_status s = check_state(c);
     if (s != PW_OK) return s;

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 namespace pw {
 
 template <typename R>
@@ -103,6 +105,11 @@ hipError_t norm2(bool dbl, const void* psi, int n, double* d_partial, int nparts
                  hipStream_t st);
 int norm2_parts(int n);
 hipError_t apply_gate2(bool dbl, void* psi, int n, int q0, int q1, const double* m16 /*host*/, hipStream_t st);
+// Two-qubit Clifford group modulo phase (host table, built once) and random brick-wall
+// circuits over it: pairs q[2g], q[2g+1] and table indices idx[g].
+int clifford2_count();
+void clifford2_matrix(int i, double* m32);
+void brickwall_clifford(int n, int n_layers, uint64_t seed, std::vector<int>& q, std::vector<int>& idx);
 hipError_t apply_diag(bool dbl, void* psi, int n, int q, const double* d2 /*host*/, hipStream_t st);
 
 // Sampling.

@@ -1,5 +1,6 @@
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based random words,
-// shared by the x samplers and the learned-proposal sampler.
+// shared by the x samplers, the learned-proposal sampler and the preconditioning
+// circuit generator.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,5 +34,6 @@ constexpr uint32_t STREAM_UNIFORM = 0x554E4946u;   // "UNIF"
 constexpr uint32_t STREAM_MARGINAL = 0x4D415247u;  // "MARG"
 constexpr uint32_t STREAM_MADE = 0x4D414445u;      // "MADE"
 constexpr uint32_t STREAM_MIX = 0x4D495843u;       // "MIXC"
+constexpr uint32_t STREAM_CLIF = 0x434C4946u;      // "CLIF"
 
 }  // namespace pw

@@ -75,3 +75,26 @@ def test_preconditioning_shallow_haar_state_reduces_r2():
     assert abs(before["M"][0] - after["M"][0]) < 1e-9
     assert after["r"][0] < before["r"][0]
     assert abs(mc["M"][0] - after["M"][0]) < 5 * mc["M_se"][0]
+
+
+@pytest.mark.parametrize("n,dtype", [(11, 0), (14, 1)])
+def test_library_preconditioning_matches_its_circuit(n, dtype):
+    # pw_precondition applies the circuit pw_precondition_circuit lists; the oracle applies
+    # that list on the CPU; exact M_alpha and the nullity are unchanged
+    psi = synth.haar_state(n, 2500 + n)
+    psi = psi.astype(np.complex64).astype(np.complex128) if dtype == 1 else psi
+    q, m = pw.pw_precondition_circuit(n, 2 * n, 77)
+    kinds = np.full(len(q), 2, dtype=np.int32)
+    ctx = make_ctx(psi, dtype)
+    log("library preconditioning n=%d dtype=%d gates=%d" % (n, dtype, len(q)))
+    before = ctx.exact(1e-7 if dtype == 0 else 1e-4)
+    ctx.precondition(2 * n, 77)
+    after = ctx.exact(1e-7 if dtype == 0 else 1e-4)
+    out = ctx.psi.cpu().numpy().astype(np.complex128)
+    ctx.close()
+    ref = oracle.apply_gates(psi, kinds, q, m)
+    assert np.max(np.abs(out - ref)) <= (1e-12 if dtype == 0 else 2e-6)
+    tol = 1e-10 if dtype == 0 else 5e-5
+    for a in range(3):
+        assert abs(after["S"][a] / before["S"][a] - 1) <= tol
+    assert after["nu_cnt"] == before["nu_cnt"]
