@@ -572,13 +572,63 @@ pw_status pw_precondition(pw_ctx c, int n_layers, uint64_t seed) {
     if (c->n < 2) return fail(PW_ERR_RANGE, "preconditioning needs n >= 2");
     if (n_layers < 0) return fail(PW_ERR_ARG, "negative layer count");
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
-    std::vector<int> q, idx;
-    brickwall_clifford(c->n, n_layers, seed, q, idx);
+    std::vector<int> q, idx, ls;
+    brickwall_clifford(c->n, n_layers, seed, q, idx, &ls);
+    ls.push_back((int)idx.size());
     const bool dbl = c->dtype == PW_C128;
-    double m32[32];
-    for (size_t g = 0; g < idx.size(); ++g) {
-        clifford2_matrix(idx[g], m32);
-        PW_HIP(apply_gate2(dbl, c->psi, c->n, q[2 * g], q[2 * g + 1], m32, c->stream));
+    const int n = c->n;
+    // The gates of a layer act on disjoint pairs (they commute) and are grouped into
+    // passes over LDS tiles: one tile of the low 12 bits, then windows of bits [0, 4)
+    // and [hb, hb + 8) that cover the remaining pairs (see apply_gates_tile).
+    auto apply_group = [&](const std::vector<int>& gs, int W, int hb, int H) -> hipError_t {
+        int a[6], b[6];
+        double m32[6 * 32];
+        int k = 0;
+        for (int g : gs) {
+            auto local = [&](int qb) { return qb < W ? qb : W + (qb - hb); };
+            a[k] = local(q[2 * g]);
+            b[k] = local(q[2 * g + 1]);
+            clifford2_matrix(idx[g], m32 + 32 * k);
+            if (++k == 6) {
+                hipError_t e = apply_gates_tile(dbl, c->psi, n, W, hb, H, k, a, b, m32, c->stream);
+                if (e != hipSuccess) return e;
+                k = 0;
+            }
+        }
+        return k ? apply_gates_tile(dbl, c->psi, n, W, hb, H, k, a, b, m32, c->stream) : hipSuccess;
+    };
+    for (size_t l = 0; l + 1 < ls.size(); ++l) {
+        std::vector<int> rem;
+        for (int g = ls[l]; g < ls[l + 1]; ++g) rem.push_back(g);
+        if (n <= 12) {
+            PW_HIP(apply_group(rem, n, n, 0));
+            continue;
+        }
+        auto in_tile = [&](int qb, int W, int hb, int H) { return qb < W || (H > 0 && qb >= hb && qb < hb + H); };
+        std::vector<int> first, rest;
+        for (int g : rem) (q[2 * g] < 12 && q[2 * g + 1] < 12 ? first : rest).push_back(g);
+        if (!first.empty()) PW_HIP(apply_group(first, 12, 12, 0));
+        while (!rest.empty()) {
+            int m = n;
+            for (int g : rest)
+                for (int j = 0; j < 2; ++j)
+                    if (q[2 * g + j] >= 4 && q[2 * g + j] < m) m = q[2 * g + j];
+            const int hb = m < n - 8 ? m : n - 8;
+            std::vector<int> take, left;
+            for (int g : rest)
+                (in_tile(q[2 * g], 4, hb, 8) && in_tile(q[2 * g + 1], 4, hb, 8) ? take : left).push_back(g);
+            if (take.empty()) {
+                // not reached for brick-wall pairs; a pair the windows cannot hold goes alone
+                const int g = rest.front();
+                double m32[32];
+                clifford2_matrix(idx[g], m32);
+                PW_HIP(apply_gate2(dbl, c->psi, n, q[2 * g], q[2 * g + 1], m32, c->stream));
+                left.assign(rest.begin() + 1, rest.end());
+            } else {
+                PW_HIP(apply_group(take, 4, hb, 8));
+            }
+            rest.swap(left);
+        }
     }
     c->cdf_valid = false;
     PW_HIP(hipStreamSynchronize(c->stream));

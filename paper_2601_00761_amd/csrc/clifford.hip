@@ -124,9 +124,11 @@ void clifford2_matrix(int i, double* m32) {
 // layers include (n-1, 0), every layer has n/2 gates), open for odd n.  Gate g of the
 // list takes table index floor(W 11520 / 2^64), W the first 64-bit word of
 // Philox4x32-10 with counter (g, 0, stream "CLIF") and key seed.
-void brickwall_clifford(int n, int n_layers, uint64_t seed, std::vector<int>& q, std::vector<int>& idx) {
+void brickwall_clifford(int n, int n_layers, uint64_t seed, std::vector<int>& q, std::vector<int>& idx,
+                        std::vector<int>* layer_start) {
     q.clear();
     idx.clear();
+    if (layer_start) layer_start->clear();
     const uint64_t order = (uint64_t)clifford2_count();
     uint64_t g = 0;
     for (int l = 0; l < n_layers; ++l) {
@@ -137,6 +139,7 @@ void brickwall_clifford(int n, int n_layers, uint64_t seed, std::vector<int>& q,
         } else {
             for (int i = start; i + 1 < n; i += 2) pairs.push_back({i, i + 1});
         }
+        if (layer_start) layer_start->push_back((int)idx.size());
         for (const auto& p : pairs) {
             uint64_t W0, W1;
             philox_words(seed, g++, 0u, STREAM_CLIF, W0, W1);

@@ -105,11 +105,16 @@ hipError_t norm2(bool dbl, const void* psi, int n, double* d_partial, int nparts
                  hipStream_t st);
 int norm2_parts(int n);
 hipError_t apply_gate2(bool dbl, void* psi, int n, int q0, int q1, const double* m16 /*host*/, hipStream_t st);
+// Up to 6 two-qubit gates (local bit positions a[g], b[g] in [0, W + H), matrices
+// m32[32 g ..] host) in one pass over tiles of bits [0, W) and [hb, hb + H), W + H <= 12.
+hipError_t apply_gates_tile(bool dbl, void* psi, int n, int W, int hb, int H, int ng, const int* a, const int* b,
+                            const double* m32, hipStream_t st);
 // Two-qubit Clifford group modulo phase (host table, built once) and random brick-wall
 // circuits over it: pairs q[2g], q[2g+1] and table indices idx[g].
 int clifford2_count();
 void clifford2_matrix(int i, double* m32);
-void brickwall_clifford(int n, int n_layers, uint64_t seed, std::vector<int>& q, std::vector<int>& idx);
+void brickwall_clifford(int n, int n_layers, uint64_t seed, std::vector<int>& q, std::vector<int>& idx,
+                        std::vector<int>* layer_start = nullptr);
 hipError_t apply_diag(bool dbl, void* psi, int n, int q, const double* d2 /*host*/, hipStream_t st);
 
 // Sampling.

@@ -81,6 +81,107 @@ k_gate2(cx<R>* __restrict__ psi, uint64_t nquad, int qlo, int qhi, int q0, int q
     }
 }
 
+// Several two-qubit gates on disjoint or overlapping pairs inside one tile of 2^T
+// amplitudes, T = W + H <= 12: the tile's index bits are [0, W) and [hb, hb + H)
+// (local index l -> l mod 2^W + (l >> W) 2^hb), the other n - T bits number the
+// tiles.  The tile is loaded into LDS once, the gates are applied in order (local bit
+// positions a[g], b[g]; matrix on the local index b_a + 2 b_b), and it is written back:
+// one pass over the state for a whole group of gates.
+constexpr int TILE_GATES_MAX = 6;
+
+template <typename R>
+struct TileGates {
+    Mat4<R> m[TILE_GATES_MAX];
+    int a[TILE_GATES_MAX], b[TILE_GATES_MAX];
+    int ng;
+};
+
+template <typename R, int T>
+__global__ void __launch_bounds__(256)
+k_gates_tile(cx<R>* __restrict__ psi, int W, int hb, int H, TileGates<R> G) {
+    constexpr uint32_t size = 1u << T;
+    constexpr int PER = size >= 256 ? (int)(size / 256) : 1;
+    __shared__ cx<R> t[size];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t tile = blockIdx.x;
+    const uint64_t tmid = tile & ((1ull << (hb - W)) - 1ull);
+    const uint64_t ttop = tile >> (hb - W);
+    cx<R>* base = psi + (tmid << W) + (ttop << (hb + H));
+    const uint32_t wm = (1u << W) - 1u;
+    // all of a thread's loads are issued before any is written to LDS
+    {
+        cx<R> v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tid + 256u * j;
+            if (i < size) v[j] = base[(i & wm) + ((size_t)(i >> W) << hb)];
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tid + 256u * j;
+            if (i < size) t[i] = v[j];
+        }
+    }
+    __syncthreads();
+    for (int g = 0; g < G.ng; ++g) {
+        const int a = G.a[g], b = G.b[g];
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        const uint32_t llo = (1u << lo) - 1u, lhi = (1u << hi) - 1u;
+        for (uint32_t k = tid; k < (size >> 2); k += 256) {
+            uint32_t q = (k & llo) | ((k & ~llo) << 1);
+            q = (q & lhi) | ((q & ~lhi) << 1);
+            const uint32_t idx[4] = {q, q | (1u << a), q | (1u << b), q | (1u << a) | (1u << b)};
+            cx<R> in[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) in[j] = t[idx[j]];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                R sr = R(0), si = R(0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const cx<R> m = G.m[g].u[4 * r + c];
+                    sr += m.re * in[c].re - m.im * in[c].im;
+                    si += m.re * in[c].im + m.im * in[c].re;
+                }
+                cx<R> o;
+                o.re = sr;
+                o.im = si;
+                t[idx[r]] = o;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const uint32_t i = tid + 256u * j;
+        if (i < size) base[(i & wm) + ((size_t)(i >> W) << hb)] = t[i];
+    }
+}
+
+template <typename R>
+hipError_t gates_tile_t(void* psi, int n, int W, int hb, int H, int ng, const int* a, const int* b,
+                        const double* m32, hipStream_t st) {
+    TileGates<R> G{};
+    G.ng = ng;
+    for (int g = 0; g < ng; ++g) {
+        G.a[g] = a[g];
+        G.b[g] = b[g];
+        for (int k = 0; k < 16; ++k) {
+            G.m[g].u[k].re = (R)m32[32 * g + 2 * k];
+            G.m[g].u[k].im = (R)m32[32 * g + 2 * k + 1];
+        }
+    }
+    const uint64_t tiles = 1ull << (n - W - H);
+    switch (W + H) {
+#define PW_TG(T) \
+    case T: hipLaunchKernelGGL((k_gates_tile<R, T>), dim3((unsigned)tiles), dim3(256), 0, st, (cx<R>*)psi, W, hb, H, G); break;
+        PW_TG(2) PW_TG(3) PW_TG(4) PW_TG(5) PW_TG(6) PW_TG(7) PW_TG(8) PW_TG(9) PW_TG(10) PW_TG(11) PW_TG(12)
+#undef PW_TG
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_diag(cx<R>* __restrict__ psi, uint64_t d, int q, cx<R> d0, cx<R> d1) {
@@ -121,6 +222,17 @@ hipError_t diag_t(void* psi, int n, int q, const double* d2, hipStream_t st) {
 }
 
 }  // namespace
+
+hipError_t apply_gates_tile(bool dbl, void* psi, int n, int W, int hb, int H, int ng, const int* a, const int* b,
+                            const double* m32, hipStream_t st) {
+    if (ng < 1 || ng > TILE_GATES_MAX || W < 0 || H < 0 || W + H > 12 || W + H > n || (H > 0 && (hb < W || hb + H > n)))
+        return hipErrorInvalidValue;
+    if (H == 0) hb = W;
+    for (int g = 0; g < ng; ++g)
+        if (a[g] < 0 || b[g] < 0 || a[g] >= W + H || b[g] >= W + H || a[g] == b[g]) return hipErrorInvalidValue;
+    return dbl ? gates_tile_t<double>(psi, n, W, hb, H, ng, a, b, m32, st)
+               : gates_tile_t<float>(psi, n, W, hb, H, ng, a, b, m32, st);
+}
 
 int norm2_parts(int n) {
     const uint64_t d = 1ull << n;

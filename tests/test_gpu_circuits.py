@@ -77,7 +77,7 @@ def test_preconditioning_shallow_haar_state_reduces_r2():
     assert abs(mc["M"][0] - after["M"][0]) < 5 * mc["M_se"][0]
 
 
-@pytest.mark.parametrize("n,dtype", [(11, 0), (14, 1)])
+@pytest.mark.parametrize("n,dtype", [(2, 0), (11, 0), (13, 1), (14, 1), (17, 0), (20, 1)])
 def test_library_preconditioning_matches_its_circuit(n, dtype):
     # pw_precondition applies the circuit pw_precondition_circuit lists; the oracle applies
     # that list on the CPU; exact M_alpha and the nullity are unchanged
