@@ -288,28 +288,48 @@ struct AccD {
 // (1-eps)^2, which is rare outside stabilizer-like families.
 template <typename R, int RL, int MOM>
 __device__ __forceinline__ AccD reduce_points(const R (&re)[1 << RL], const R (&im)[1 << RL], bool x0, R eps) {
-    R s1 = R(0), s2 = R(0), s3 = R(0), s4 = R(0), ent = R(0), mx = R(0);
-    auto acc = [&](R t) {
-        s1 += t;
-        const R t2 = t * t;
-        s2 += t2;
-        if constexpr (MOM >= 3) s3 = fma(t2, t, s3);
-        if constexpr (MOM >= 4) s4 = fma(t2, t2, s4);
-        ent = fma(t, Math<R>::lg2(fmax(t, Math<R>::tiny)), ent);
-        mx = fmax(mx, t);
-    };
-    if (x0) {
+    // transform-precision partial sums over at most 16 points (32 magnitudes), then FP64
+    constexpr int CH = (1 << RL) < 16 ? (1 << RL) : 16;
+    double D1, D2, D3, D4, DE;
+    R mx = R(0);
 #pragma unroll
-        for (int j = 0; j < (1 << RL); ++j) {
-            const R u = re[j] + im[j], v = re[j] - im[j];
-            acc(u * u);
-            acc(v * v);
+    for (int c0 = 0; c0 < (1 << RL); c0 += CH) {
+        R s1 = R(0), s2 = R(0), s3 = R(0), s4 = R(0), ent = R(0);
+        auto acc = [&](R t) {
+            s1 += t;
+            const R t2 = t * t;
+            s2 += t2;
+            if constexpr (MOM >= 3) s3 = fma(t2, t, s3);
+            if constexpr (MOM >= 4) s4 = fma(t2, t2, s4);
+            ent = fma(t, Math<R>::lg2(fmax(t, Math<R>::tiny)), ent);
+            mx = fmax(mx, t);
+        };
+        if (x0) {
+#pragma unroll
+            for (int j = c0; j < c0 + CH; ++j) {
+                const R u = re[j] + im[j], v = re[j] - im[j];
+                acc(u * u);
+                acc(v * v);
+            }
+        } else {
+#pragma unroll
+            for (int j = c0; j < c0 + CH; ++j) {
+                acc(re[j] * re[j]);
+                acc(im[j] * im[j]);
+            }
         }
-    } else {
-#pragma unroll
-        for (int j = 0; j < (1 << RL); ++j) {
-            acc(re[j] * re[j]);
-            acc(im[j] * im[j]);
+        if (c0 == 0) {
+            D1 = (double)s1;
+            D2 = (double)s2;
+            D3 = (double)s3;
+            D4 = (double)s4;
+            DE = (double)ent;
+        } else {
+            D1 += (double)s1;
+            D2 += (double)s2;
+            D3 += (double)s3;
+            D4 += (double)s4;
+            DE += (double)ent;
         }
     }
     const R sc = x0 ? R(1) : R(4);
@@ -339,11 +359,11 @@ __device__ __forceinline__ AccD reduce_points(const R (&re)[1 << RL], const R (&
     }
     AccD d;
     const double scd = (double)sc;
-    d.s1 = scd * (double)s1;
-    d.s2 = scd * scd * (double)s2;
-    d.s3 = scd * scd * scd * (double)s3;
-    d.s4 = scd * scd * scd * scd * (double)s4;
-    d.ent = x0 ? (double)ent : 4.0 * (double)ent + 8.0 * (double)s1;
+    d.s1 = scd * D1;
+    d.s2 = scd * scd * D2;
+    d.s3 = scd * scd * scd * D3;
+    d.s4 = scd * scd * scd * scd * D4;
+    d.ent = x0 ? DE : 4.0 * DE + 8.0 * D1;
     d.gap = gap >= R(0) ? scd * (double)gap : -1.0;
     d.cnt = cnt;
     return d;
