@@ -67,7 +67,7 @@ typedef enum {
     PW_ERR_WORKSPACE = 5,       /* workspace too small                             */
     PW_ERR_HIP = 6,             /* a HIP runtime call failed                       */
     PW_ERR_TOLERANCE = 7,       /* nullity count is not a power of two            */
-    PW_ERR_UNSUPPORTED = 8      /* valid request this build does not handle        */
+    PW_ERR_UNSUPPORTED = 8      /* valid request the library does not handle       */
 } pw_status;
 
 typedef enum { PW_C128 = 0, PW_C64 = 1 } pw_dtype;
