@@ -28,8 +28,11 @@ N_QUBITS = 20
 ETA = 20
 N_T = 20
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU issue peak with packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# FP32 VALU peak in lane-operations/s: the published 157.3 TFLOP/s FP32 vector rate counts
+# an FMA as two operations, i.e. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6e12 VALU
+# lane-operations/s (a dependent-free add chain with vector operands reaches 74e12 here,
+# with packed FP32 disabled); an add, a multiply or an FMA counts as one operation.
+VALU_PEAK_GOPS = 256 * 4 * 32 * 2.4
 KCLASS = {0: "k_fused", 1: "k_first", 2: "k_column(mid)", 3: "k_column(last)"}
 # kernel-name prefixes as rocprofv3 reports them (first pass: shared-tile variant for sweeps)
 KNAME = {0: "k_fused", 1: "k_first_shared", 2: "k_column", 3: "k_column"}
