@@ -173,6 +173,84 @@ def mc_leg(pw, torch, stream, eta, timing_every):
                                  "rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per family of the first and reducing passes"}}
 
 
+MULTI_STATES = 64
+MULTI_X = 64
+
+
+def multistate_leg(pw, torch, stream):
+    """Many states of uneven size in one call: 32 Haar and 32 T-doped states (eta = N/2,
+    N_T = N, from |0...0>), N uniform in 16..24, each evaluated on x = 0 and 63 draws from
+    its exact marginal through pw_eval_states; complex64 (FP32 transform) and complex128
+    (FP64).  Reported: Pauli strings/s of each, and per state the largest relative
+    difference of m_{2;x} between the two paths and, for N <= 20, against the FP64 oracle
+    on x = 0 and the first draw.  State preparation and the draws are untimed."""
+    import numpy as np
+    import oracle
+    import synth
+    seed = synth.SEED_BASE + 4
+    ns = [16 + int(v % np.uint64(9)) for v in synth.splitmix64(seed, 0, MULTI_STATES)]
+    dev = "cuda:0"
+    st128, kinds = [], []
+    ctx = pw.Context(0, stream)
+    for k, n in enumerate(ns):
+        if k < MULTI_STATES // 2:
+            t = torch.from_numpy(synth.haar_state(n, seed + 1000 + k)).to(dev)
+            kinds.append("haar")
+        else:
+            t = torch.zeros(1 << n, dtype=torch.complex128, device=dev)
+            t[0] = 1.0
+            ctx.bind(t, pw.PW_C128)
+            ctx.apply_gates(*synth.gates_to_arrays(synth.tdoped_stream(n, n // 2, n, seed + 2000 + k)))
+            kinds.append("tdoped")
+        st128.append(t)
+    st64 = [t.to(torch.complex64) for t in st128]
+    xs, idx = [], []
+    for k, t in enumerate(st128):
+        ctx.bind(t, pw.PW_C128)
+        draws = ctx.sample_x(pw.PW_SAMPLER_MARGINAL_NZ, seed + 3000 + k, 0, MULTI_X - 1)
+        xs += [0] + [int(v) for v in draws]
+        idx += [k] * MULTI_X
+    xs = np.array(xs, dtype=np.uint64)
+    idx = np.array(idx, dtype=np.int32)
+    strings = float(sum(MULTI_X * (1 << n) for n in ns))
+    pw.pw_set_moments(ctx.h, 2)
+    out = {}
+    res = {}
+    for name, states, dt, eps in (("c64", st64, pw.PW_C64, 1e-4), ("c128", st128, pw.PW_C128, 1e-7)):
+        refs = [(t, n, dt) for t, n in zip(states, ns)]
+        pw.pw_eval_states(ctx.h, refs, idx[:MULTI_X], xs[:MULTI_X], eps)      # warm-up: workspace, kernels
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pw.pw_eval_states(ctx.h, refs, idx, xs, eps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = r
+        out[name] = {"seconds": el, "pauli_strings_per_s": strings / el}
+    ctx.close()
+    per = []
+    for k, n in enumerate(ns):
+        sl = slice(k * MULTI_X, (k + 1) * MULTI_X)
+        m32, m64 = res["c64"]["m"][sl, 0], res["c128"]["m"][sl, 0]
+        e = {"n": n, "kind": kinds[k],
+             "max_rel_m2_fp32_vs_fp64": float(np.max(np.abs(m32 - m64) / np.maximum(np.abs(m64), 1e-300)))}
+        if n <= 20:
+            psi = st128[k].cpu().numpy()
+            o = oracle.eval_x(psi, xs[sl][[0, 1]], eps=1e-7, max_alpha=2)
+            e["oracle_max_rel_m2_fp64"] = float(np.max(np.abs(m64[:2] - o["m"][:, 0]) / np.abs(o["m"][:, 0])))
+            psi32 = st64[k].cpu().numpy().astype(np.complex128)
+            o32 = oracle.eval_x(psi32, xs[sl][[0, 1]], eps=1e-4, max_alpha=2)
+            e["oracle_max_rel_m2_fp32"] = float(np.max(np.abs(m32[:2] - o32["m"][:, 0]) / np.abs(o32["m"][:, 0])))
+        per.append(e)
+    out.update({"workload": "64 states (32 Haar, 32 T-doped eta=N/2 N_T=N), N uniform in 16..24, x = 0 plus 63 "
+                            "exact-marginal draws per state, one pw_eval_states call",
+                "n_values": ns, "families": len(xs), "pauli_strings": strings,
+                "max_rel_m2_fp32_vs_fp64": max(p["max_rel_m2_fp32_vs_fp64"] for p in per),
+                "max_rel_m2_fp64_vs_oracle": max(p.get("oracle_max_rel_m2_fp64", 0.0) for p in per),
+                "max_rel_m2_fp32_vs_oracle": max(p.get("oracle_max_rel_m2_fp32", 0.0) for p in per),
+                "per_state": per})
+    return out
+
+
 LEARNED_N = 30
 
 
@@ -251,6 +329,8 @@ def main():
                     help="families per launch (0: the library default for the state size)")
     ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=None,
                     help="also run the N=30 learned-vs-plain proposal comparison (minutes; off by default)")
+    ap.add_argument("--multistate-leg", action="store_true",
+                    help="also run the 64-state uneven-N batch (minute-scale; off by default)")
     ap.add_argument("--learned-draws", type=int, default=2048)
     ap.add_argument("--learned-pilot", type=int, default=4096)
     ap.add_argument("--max-alpha", type=int, default=2, choices=(2, 4),
@@ -378,6 +458,8 @@ def main():
                        "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0]}
     if not args.no_mc_leg:
         out["m2_wall_time"] = [mc_leg(pw, torch, stream, eta, args.timing_every) for eta in args.mc_eta]
+    if args.multistate_leg:
+        out["multi_state"] = multistate_leg(pw, torch, stream)
     if args.learned_leg is not None:
         kinds = args.learned_leg or ["psi_m", "tdoped"]
         out["learned_vs_plain"] = [learned_leg(pw, torch, stream, k, args.learned_draws, args.learned_pilot)

@@ -274,9 +274,9 @@ PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out)
 PW_API pw_status pw_autotune(pw_ctx ctx, int* best_batch, int* candidates, double* us_per_family, int* n_candidates);
 
 /* Several states of different sizes in one call: family xs[i] of state
- * states[state_idx[i]], results to out[i] (host arrays).  The workspace is carved
- * once for the largest state and shared; every state is norm-checked.  The bound
- * state of the context is kept. */
+ * states[state_idx[i]], results to out[i] (host arrays).  One workspace serves all
+ * states, sized for the largest layout; each state runs at its own families per
+ * launch; every state is norm-checked.  The bound state of the context is kept. */
 typedef struct {
     void* psi;         /* device amplitudes, 256-byte aligned, borrowed */
     int n;

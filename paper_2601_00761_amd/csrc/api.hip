@@ -1327,19 +1327,21 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         if (state_idx[i] < 0 || state_idx[i] >= nstates) return fail(PW_ERR_ARG, "state_idx[%lld] out of range", (long long)i);
         if (xs[i] >> states[state_idx[i]].n) return fail(PW_ERR_RANGE, "xs[%lld] not below 2^n of its state", (long long)i);
     }
-    // one workspace carve shared by all states: the batch of the most demanding state,
-    // and room for the largest layout at that batch
-    int B = MAX_BATCH;
-    for (int k = 0; k < nstates; ++k) B = std::min(B, default_batch(states[k].n, states[k].dtype));
-    auto need_for = [&](int b) {
-        size_t need = 0;
-        for (int k = 0; k < nstates; ++k) need = std::max(need, layout_for(states[k].n, states[k].dtype, b).total);
-        return need;
-    };
+    // one workspace shared by all states; each state runs at its own families-per-launch
+    // (its default, shrunk to fit a caller-owned workspace), and the workspace holds the
+    // largest of those layouts
+    std::vector<int> Bk((size_t)nstates);
+    size_t need = 0;
+    for (int k = 0; k < nstates; ++k) {
+        int b = default_batch(states[k].n, states[k].dtype);
+        if (c->ws && !c->ws_owned)
+            while (b > 1 && layout_for(states[k].n, states[k].dtype, b).total > c->ws_bytes) b /= 2;
+        Bk[(size_t)k] = b;
+        need = std::max(need, layout_for(states[k].n, states[k].dtype, b).total);
+    }
     if (c->ws && !c->ws_owned) {
-        while (B > 1 && need_for(B) > c->ws_bytes) B /= 2;
-        if (need_for(B) > c->ws_bytes) return fail(PW_ERR_WORKSPACE, "workspace too small for the largest state");
-    } else if (!c->ws || c->ws_bytes < need_for(B)) {
+        if (need > c->ws_bytes) return fail(PW_ERR_WORKSPACE, "workspace too small for the largest state");
+    } else if (!c->ws || c->ws_bytes < need) {
         if (c->ws) {
             PW_HIP(hipStreamSynchronize(c->stream));
             PW_HIP(hipFree(c->ws));
@@ -1348,9 +1350,9 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         }
         if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
         void* p = nullptr;
-        PW_HIP(hipMalloc(&p, need_for(B)));
+        PW_HIP(hipMalloc(&p, need));
         c->ws = (char*)p;
-        c->ws_bytes = need_for(B);
+        c->ws_bytes = need;
         c->ws_owned = true;
     }
     const bool was_bound = c->bound;
@@ -1374,13 +1376,15 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         c->n = states[k].n;
         c->dtype = states[k].dtype;
         c->P = make_plan(c->n, c->dtype == PW_C128);
+        const int B = Bk[(size_t)k];
         c->L = layout_for(c->n, c->dtype, B);
         if (c->L.total > cap) {
             s = fail(PW_ERR_WORKSPACE, "state %d does not fit the shared workspace", k);
             break;
         }
         c->batch = B;
-        c->run_batch = B;
+        const int tuned = tuned_batch(c->device, c->n, c->dtype);
+        c->run_batch = tuned > 0 && tuned < B ? tuned : B;
         c->cdf_valid = false;
         double nrm = 0.0;
         s = run_norm(c, &nrm);
