@@ -7,8 +7,8 @@ x_B = 0 and |x_A| = k, else 0; the same product argument gives 2^{-(N+h)-k} for
 odd N), with p(x) = 2^{-h} [x_B = 0] (product of one-qubit marginals: 1/2, 1/2 for
 |T>, 1, 0 for |0>) and nu_x = 2^{N-h} for x = 0, else 0;
 (b) Clifford invariance of M_2 (Clifford preconditioning section) through the
-Monte Carlo estimator at N = 28; (c) per-family oracle values on sampled x for a
-Haar state at N = 26.
+Monte Carlo estimator at N = 28; (c) per-family oracle values on sampled x for Haar
+states at N = 25, 26, 27.
 """
 import math
 
@@ -88,13 +88,12 @@ def test_scrambled_psi_m_monte_carlo_n28():
     assert abs(res["M"][0] - exact) < 5 * res["M_se"][0] + 2e-3
 
 
-@pytest.mark.parametrize("dtype", [1, 0])
-def test_haar_n26_sampled_families_vs_oracle(dtype):
-    n = 26
-    psi = synth.haar_state(n, synth.SEED_BASE + 26)
+@pytest.mark.parametrize("n,dtype", [(26, 1), (26, 0), (25, 1), (27, 1)])
+def test_haar_large_sampled_families_vs_oracle(n, dtype):
+    psi = synth.haar_state(n, synth.SEED_BASE + n)
     if dtype == pw.PW_C64:
         psi = psi.astype(np.complex64).astype(np.complex128)
-    xs = np.array([0, 3, 1 << 20, (1 << n) - 1], dtype=np.uint64)
+    xs = np.array([0, 3, 1 << 20, (1 << n) - 1] if n <= 26 else [5, (1 << n) - 1], dtype=np.uint64)
     log("haar n=%d dtype=%d" % (n, dtype))
     ctx = pw.Context(0)
     ctx.upload(psi, dtype)
