@@ -62,6 +62,7 @@ size_t esize(pw_dtype dt) { return dt == PW_C128 ? 16 : 8; }
 struct Layout {
     size_t work, parts, xs, xres, fam, sweep, cdf, cdfblk, norm, ctr, total;
     int64_t parts_fams;  // families whose final-pass partials the parts region holds
+    int64_t xcap;        // x values / per-family results the staging regions hold
 };
 
 // Partials of several batches are kept (up to 16 batches, 16 MiB) so that one
@@ -89,10 +90,13 @@ Layout layout_for(int n, pw_dtype dt, int batch) {
     if (group > (size_t)PARTS_GROUP_MAX) group = PARTS_GROUP_MAX;
     L.parts_fams = (int64_t)group * batch;
     off += align256(group * per_batch);
+    // x lists and per-family results are staged MAX_BATCH at a time whatever the batch, so
+    // that host lists cross the bus in few copies and Monte Carlo steps hold a whole batch
+    L.xcap = MAX_BATCH;
     L.xs = off;
-    off += align256((size_t)batch * sizeof(uint64_t));
+    off += align256((size_t)L.xcap * sizeof(uint64_t));
     L.xres = off;
-    off += align256((size_t)batch * sizeof(FamilyRes));
+    off += align256((size_t)L.xcap * sizeof(FamilyRes));
     L.fam = off;
     const int64_t chunk = ((int64_t)1 << n) < EXACT_CHUNK ? ((int64_t)1 << n) : EXACT_CHUNK;
     off += align256((size_t)chunk * sizeof(FamilyRes));
@@ -302,7 +306,8 @@ pw_status run_norm(pw_ctx c, double* out) {
 
 // Evaluate nx families whose x are in device memory (or x0 + i when d_xs is null),
 // results to device array d_out.  Chunked by the context batch.
-pw_status eval_device(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out) {
+pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
+                         hipStream_t st) {
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
     const bool dbl = c->dtype == PW_C128;
     // multi-pass plans: batches leave their partials side by side, one finalize per group
@@ -312,24 +317,28 @@ pw_status eval_device(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, d
     for (int64_t i = 0; i < nx; i += c->run_batch) {
         const int nb = (int)((nx - i) < c->run_batch ? (nx - i) : c->run_batch);
         if (defer && pending + nb > c->L.parts_fams) {
-            PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, c->stream));
+            PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, st));
             g0 = i;
             pending = 0;
         }
         PW_HIP(eval_batch(c->P, dbl, c->max_alpha, c->psi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
-                          c->ws + c->L.work, parts + (size_t)pending * c->P.blocks_last, d_out + i, c->stream,
+                          c->ws + c->L.work, parts + (size_t)pending * c->P.blocks_last, d_out + i, st,
                           timer_of(c), !defer));
         pending += nb;
     }
-    if (defer && pending > 0) PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, c->stream));
+    if (defer && pending > 0) PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, st));
     return PW_OK;
+}
+
+pw_status eval_device(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out) {
+    return eval_device_on(c, d_xs, x0, nx, eps, d_out, c->stream);
 }
 
 pw_status eval_host(pw_ctx c, const uint64_t* xs, int64_t nx, double eps, FamilyRes* out) {
     uint64_t* dx = at<uint64_t>(c, c->L.xs);
     FamilyRes* dr = at<FamilyRes>(c, c->L.xres);
-    for (int64_t i = 0; i < nx; i += c->batch) {
-        const int nb = (int)((nx - i) < c->batch ? (nx - i) : c->batch);
+    for (int64_t i = 0; i < nx; i += c->L.xcap) {
+        const int nb = (int)((nx - i) < c->L.xcap ? (nx - i) : c->L.xcap);
         if (fault("copy")) return fail(PW_ERR_HIP, "hipMemcpy: injected failure (PW_FAULT=copy)");
         PW_HIP(hipMemcpyAsync(dx, xs + i, nb * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
         pw_status s = eval_device(c, dx, 0, nb, eps, dr);
@@ -372,8 +381,9 @@ pw_status mc_step_enqueue(pw_ctx c, pw_sampler sampler, uint64_t seed, int nb, d
     uint64_t* dctr = at<uint64_t>(c, c->L.ctr);
     if (sampler == PW_SAMPLER_UNIFORM_NZ) PW_HIP(sample_uniform(c->n, seed, 0, nb, dx, st, dctr));
     else PW_HIP(sample_marginal(c->n, at<double>(c, c->L.cdf), seed, 0, nb, dx, st, dctr));
-    PW_HIP(eval_batch(c->P, c->dtype == PW_C128, c->max_alpha, c->psi, dx, 0, nb, eps, c->ws + c->L.work,
-                      at<FamilyRes>(c, c->L.parts), at<FamilyRes>(c, c->L.xres), st, nullptr));
+    // the families in chunks of the launch batch
+    const pw_status s = eval_device_on(c, dx, 0, nb, eps, at<FamilyRes>(c, c->L.xres), st);
+    if (s != PW_OK) return s;
     PW_HIP(bump_counter(dctr, (uint64_t)nb, st));
     return PW_OK;
 }
@@ -691,8 +701,8 @@ pw_status pw_sample_x(pw_ctx c, pw_sampler sampler, uint64_t seed, uint64_t offs
         PW_HIP(build_cdf(c->dtype == PW_C128, c->psi, c->n, at<double>(c, c->L.cdf), at<double>(c, c->L.cdfblk), c->stream));
         c->cdf_valid = true;
     }
-    for (int64_t i = 0; i < n; i += c->batch) {
-        const int64_t nb = (n - i) < c->batch ? (n - i) : c->batch;
+    for (int64_t i = 0; i < n; i += c->L.xcap) {
+        const int64_t nb = (n - i) < c->L.xcap ? (n - i) : c->L.xcap;
         if (sampler == PW_SAMPLER_UNIFORM_NZ) PW_HIP(sample_uniform(c->n, seed, offset + (uint64_t)i, nb, dx, c->stream));
         else PW_HIP(sample_marginal(c->n, at<double>(c, c->L.cdf), seed, offset + (uint64_t)i, nb, dx, c->stream));
         PW_HIP(hipMemcpyAsync(xs_out + i, dx, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
@@ -782,7 +792,7 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
     std::vector<FamilyRes> res;
     const uint64_t draws_max = max_samples - 1;
     int batches = 0;
-    const bool graphs = c->use_graphs && batch <= c->batch;
+    const bool graphs = c->use_graphs && batch <= c->L.xcap;
     McGraph g;
     if (graphs) {
         if (sampler == PW_SAMPLER_MARGINAL_NZ && !c->cdf_valid) {
