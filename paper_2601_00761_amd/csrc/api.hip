@@ -50,7 +50,7 @@ bool fault(const char* what) {
 constexpr int MAX_QUBITS = 32;
 constexpr int EXACT_MAX_QUBITS = 26;
 constexpr int FAMILY_VALUES_MAX_QUBITS = 26;
-constexpr int SWEEP_SLOTS = 4096;    // per-chunk sums of an exact sweep
+constexpr int SWEEP_SLOTS = 16384;   // partial sums of an exact sweep (4096 families each)
 constexpr int64_t EXACT_CHUNK = 1 << 20;  // families per chunk of an exact sweep
 constexpr int MAX_BATCH = 4096;
 
@@ -727,9 +727,9 @@ pw_status pw_exact(pw_ctx c, double eps, pw_result* out) {
         const int64_t cnt = (int64_t)((d - c0) < (uint64_t)EXACT_CHUNK ? (d - c0) : (uint64_t)EXACT_CHUNK);
         s = eval_device(c, nullptr, c0, cnt, eps, fam);
         if (s != PW_OK) return s;
-        if (nchunk == SWEEP_SLOTS) return fail(PW_ERR_UNSUPPORTED, "too many chunks");
+        if (nchunk + reduce_families_slots(cnt) > SWEEP_SLOTS) return fail(PW_ERR_UNSUPPORTED, "too many chunks");
         PW_HIP(reduce_families(fam, cnt, sw + nchunk, c->stream));
-        ++nchunk;
+        nchunk += reduce_families_slots(cnt);
     }
     PW_HIP(reduce_sweep(sw, nchunk, fin, c->stream));
     SweepSums h;
@@ -1243,8 +1243,9 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
     }
     SweepSums* sw = at<SweepSums>(c, c->L.sweep);
     PW_HIP(reduce_families(fam, (int64_t)dA, sw, c->stream));
+    PW_HIP(reduce_sweep(sw, reduce_families_slots((int64_t)dA), sw + SWEEP_SLOTS, c->stream));
     SweepSums h;
-    PW_HIP(hipMemcpyAsync(&h, sw, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipMemcpyAsync(&h, sw + SWEEP_SLOTS, sizeof h, hipMemcpyDeviceToHost, c->stream));
     PW_HIP(hipStreamSynchronize(c->stream));
     pw_mixed_result r;
     memset(&r, 0, sizeof r);

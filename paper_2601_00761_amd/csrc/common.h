@@ -90,6 +90,10 @@ hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, 
                               FamilyRes* out, hipStream_t st);
 
 // Fixed-order sum of count per-family results.
+// Partial sums of count per-family results, FAM_PER_SLOT families per slot, written to
+// out[0 .. reduce_families_slots(count)) in family order.
+constexpr int64_t FAM_PER_SLOT = 4096;
+inline int64_t reduce_families_slots(int64_t count) { return (count + FAM_PER_SLOT - 1) / FAM_PER_SLOT; }
 hipError_t reduce_families(const FamilyRes* in, int64_t count, SweepSums* out, hipStream_t st);
 
 // Transform only (no reductions): writes the 2^nh half-spectrum G of one x into work.

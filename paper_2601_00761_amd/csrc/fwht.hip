@@ -820,14 +820,17 @@ __device__ __forceinline__ void add_sums(SweepSums& a, const SweepSums& b) {
     }
 }
 
-// Fixed-order sum of count per-family results into one SweepSums.
+// Fixed-order sums of per-family results: block b sums families [b F, (b+1) F) of the
+// count, F = FAM_PER_SLOT, into out[b].
 __global__ void __launch_bounds__(256)
 k_reduce_fam(const FamilyRes* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
     constexpr int NT = 256;
     __shared__ SweepSums sh[NT];
     SweepSums t;
     zero_sums(t);
-    for (int64_t i = threadIdx.x; i < count; i += NT) {
+    const int64_t b0 = (int64_t)blockIdx.x * FAM_PER_SLOT;
+    const int64_t b1 = b0 + FAM_PER_SLOT < count ? b0 + FAM_PER_SLOT : count;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) {
         const FamilyRes v = in[i];
         t.S[0] += v.m[0];
         t.S[1] += v.m[1];
@@ -850,7 +853,7 @@ k_reduce_fam(const FamilyRes* __restrict__ in, int64_t count, SweepSums* __restr
         if ((int)threadIdx.x < h) add_sums(sh[threadIdx.x], sh[threadIdx.x + h]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
 }
 
 __global__ void __launch_bounds__(256)
@@ -1195,7 +1198,8 @@ hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, 
 }
 
 hipError_t reduce_families(const FamilyRes* in, int64_t count, SweepSums* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_fam, dim3(1), dim3(256), 0, st, in, count, out);
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_fam, dim3((unsigned)reduce_families_slots(count)), dim3(256), 0, st, in, count, out);
     return hipGetLastError();
 }
 
