@@ -922,6 +922,9 @@ __global__ void k_signed(const cx<R>* __restrict__ G, int n, uint32_t x, double*
 // K = 13 (512 x 16, 70 KB) when that saves a pass; fused kernels K = n - 1.
 constexpr int K_FIRST = 12;
 constexpr int COL_RL = 4;
+#ifndef COL15_LTL
+#define COL15_LTL 9
+#endif
 
 template <typename R, int K, int MOM>
 hipError_t launch_fused_k(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
@@ -1000,8 +1003,13 @@ hipError_t launch_column15(int s, dim3 grid, cx<float>* work, int n, int lo, con
     switch (s) {
 #define PW_COL15(S)                                                                                                \
     case S:                                                                                                        \
-        PW_LAUNCH(tm, kc, (int)grid.y, (k_column<float, 10, 5, S, LAST, MOM, true>), grid, dim3(1024), st, work, n, \
-                  lo, xs, x0, eps, parts);                                                                         \
+        if constexpr (LAST) {                                                                                      \
+            PW_LAUNCH(tm, kc, (int)grid.y, (k_column<float, COL15_LTL, 15 - COL15_LTL, S, LAST, MOM, true>), grid,    \
+                      dim3(1 << COL15_LTL), st, work, n, lo, xs, x0, eps, parts);                                     \
+        } else {                                                                                                   \
+            PW_LAUNCH(tm, kc, (int)grid.y, (k_column<float, 10, 5, S, LAST, MOM, true>), grid, dim3(1024), st, work, \
+                      n, lo, xs, x0, eps, parts);                                                                  \
+        }                                                                                                          \
         return hipGetLastError();
         PW_COL15(9) PW_COL15(10) PW_COL15(11) PW_COL15(12)
 #undef PW_COL15
