@@ -130,25 +130,30 @@ __device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<
 
 // The same move for tiles too large for one complex LDS buffer (2^15 single-
 // precision points = 256 KB > 160 KB): real parts first, then imaginary parts,
-// through a float buffer padded one element in 32.
-__host__ __device__ constexpr uint32_t pad32c(uint32_t i) { return i + (i >> 5); }
+// through a float buffer padded one element in 2^RL.  A thread part that strides
+// 2^(A + RL) between groups of 2^A lanes then lands each group on its own bank range
+// (64 banks; RL = 5 or 6 with A = 3 gives 8 groups of 8 lanes, RL = 5 with A = 0
+// one lane per bank).
+template <int RL>
+__host__ __device__ constexpr uint32_t pads(uint32_t i) { return i + (i >> RL); }
 
 template <typename R, int TL, int RL, int AO, int AN>
 __device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL], R* buf) {
+    static_assert(RL >= 5, "the split buffer is sized for one pad element in 32 or fewer");
     const uint32_t tid = threadIdx.x;
-    R* wo = buf + pad32c(thread_part<AO, RL>(tid));
-    const R* rn = buf + pad32c(thread_part<AN, RL>(tid));
+    R* wo = buf + pads<RL>(thread_part<AO, RL>(tid));
+    const R* rn = buf + pads<RL>(thread_part<AN, RL>(tid));
 #pragma unroll
-    for (int j = 0; j < (1 << RL); ++j) wo[pad32c((uint32_t)j << AO)] = re[j];
+    for (int j = 0; j < (1 << RL); ++j) wo[pads<RL>((uint32_t)j << AO)] = re[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < (1 << RL); ++j) re[j] = rn[pad32c((uint32_t)j << AN)];
+    for (int j = 0; j < (1 << RL); ++j) re[j] = rn[pads<RL>((uint32_t)j << AN)];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < (1 << RL); ++j) wo[pad32c((uint32_t)j << AO)] = im[j];
+    for (int j = 0; j < (1 << RL); ++j) wo[pads<RL>((uint32_t)j << AO)] = im[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < (1 << RL); ++j) im[j] = rn[pad32c((uint32_t)j << AN)];
+    for (int j = 0; j < (1 << RL); ++j) im[j] = rn[pads<RL>((uint32_t)j << AN)];
     __syncthreads();
 }
 
