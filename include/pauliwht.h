@@ -285,11 +285,12 @@ typedef struct {
 PW_API pw_status pw_eval_states(pw_ctx ctx, int nstates, const pw_state_ref* states, const int* state_idx,
                                 const uint64_t* xs, int64_t n_x, double eps, pw_xres* out);
 
-/* Graph replay for pw_mc: when enabled, one sampling step (device-side draws whose
- * counters come from a device counter, evaluation of their families, counter
- * increment) is captured once per pw_mc call as a HIP graph on a private
- * non-blocking stream and replayed for every full batch of size <= the workspace
- * batch.  Results are bitwise those of the eager path. */
+/* Graph replay for pw_mc (off by default): when enabled, one sampling step
+ * (device-side draws whose counters come from a device counter, evaluation of their
+ * families in launches of the workspace batch, counter increment) is captured once
+ * per pw_mc call as a HIP graph on a private non-blocking stream and replayed for
+ * every full step; steps of up to 4096 draws.  Results are bitwise those of the
+ * eager path.  Launches inside replays are not seen by pw_timing_*. */
 PW_API pw_status pw_set_graphs(pw_ctx ctx, int enable);
 
 /* Highest moment order computed per family: 4 (default: alpha = 2, 3, 4) or 2
@@ -299,9 +300,10 @@ PW_API pw_status pw_set_moments(pw_ctx ctx, int max_alpha);
 
 /* Measurement support.  pw_timing_enable(ctx, k) attaches a pair of HIP events to
  * the dispatch of every k-th launch of each kernel class (k = 0 disables; the
- * events bracket the kernel's execution on the context stream): class 0 = single-workgroup family kernel (small n), 1 = first
- * transform pass (products + low 12 index bits), 2 = middle column pass,
- * 3 = final column pass with the reductions.  pw_timing_read synchronises the
+ * events bracket the kernel's execution on the context stream): class 0 =
+ * single-workgroup family kernel (small n), 1 = first transform pass (products and
+ * the low 12 index bits, 15 for single precision n = 23..28), 2 = middle column
+ * pass, 3 = final column pass with the reductions.  pw_timing_read synchronises the
  * recorded events and returns, for one class, the number of timed launches,
  * their summed duration in milliseconds and the families they processed.
  * pw_timing_reset clears the accumulators. */
