@@ -154,6 +154,9 @@ def mc_leg(pw, torch, stream, eta, timing_every):
         cnt, ms, fam = pw.pw_timing_read(ctx.h, k)
         if cnt:
             kt[KCLASS[k]] = dict(launches=cnt, avg_us=round(1e3 * ms / cnt, 2), families_per_launch=fam / cnt)
+    pw.pw_timing_enable(ctx.h, 0)
+    # context: the paper's own estimator (x uniform over x != 0) on the same state, 1024 draws
+    uni = ctx.mc(pw.PW_SAMPLER_UNIFORM_NZ, 1e-4, MC_BATCH, 1025, 0.0, seed + 6)
     ctx.close()
     fams = res["n_samples"]
     # HBM roofline of the evaluation path: one read of psi (2^N x 8 B) per family is the
@@ -169,6 +172,11 @@ def mc_leg(pw, torch, stream, eta, timing_every):
                         "std-err(M_2) <= %g or %d families" % (n, eta, 2 * n, 2 * n, MC_BATCH, MC_TARGET_SE, MC_MAX),
             "eta": eta, "M2": res["M"][0], "M2_se": res["M_se"][0], "M1": res["M1"], "M1_se": res["M1_se"],
             "r2": res["r"][0], "n_samples": fams, "target_reached": bool(res["M_se"][0] <= MC_TARGET_SE),
+            "families_for_se_target": fams * (res["M_se"][0] / MC_TARGET_SE) ** 2,
+            "uniform_sampler_context": {
+                "note": "the paper's estimator (x uniform over x != 0, plus x = 0) on the same state, 1024 draws",
+                "M2": uni["M"][0], "M2_se": uni["M_se"][0], "r2": uni["r"][0],
+                "families_for_se_target": uni["n_samples"] * (uni["M_se"][0] / MC_TARGET_SE) ** 2},
             "wall_s": t2 - t0, "precondition_s": t1 - t0, "mc_s": t2 - t1,
             "pauli_strings_per_s_mc": fams * float(1 << n) / (t2 - t1),
             "kernels": kt,
