@@ -1,4 +1,4 @@
-"""Full-size checks (N = 23..30) through the C ABI.
+"""Full-size checks (N = 23..32) through the C ABI.
 
 At these sizes the oracle cannot enumerate, so the checks use (a) the paper's
 closed forms for the product magic state |psi_m> = |T>^h |0>^{N-h}, h = floor(N/2)
@@ -67,6 +67,27 @@ def test_psi_m_closed_forms_full_size(n):
     del psi
     g = ctx.eval_x(xs, 1e-4)
     ctx.close()
+    psi_m_checks(n, g, xs)
+
+
+@pytest.mark.parametrize("n", [31, 32])
+def test_psi_m_closed_forms_largest_sizes(n):
+    # the largest states the library takes (2^32 complex64 amplitudes = 32 GiB), built on
+    # the device: every index of the multi-pass plan beyond 2^31 is exercised
+    import torch
+    h = n // 2
+    psi = torch.zeros(1 << n, dtype=torch.complex64, device="cuda:0")
+    b = np.arange(1 << h)
+    pc = np.array([bin(int(v)).count("1") for v in b])
+    psi[: 1 << h] = torch.from_numpy(((2.0 ** (-h / 2)) * np.exp(1j * np.pi / 4 * pc)).astype(np.complex64)).cuda()
+    xs = _xs_for(n, 1000 + n)
+    log("psi_m closed forms n=%d nx=%d (device-built state)" % (n, len(xs)))
+    ctx = pw.Context(0)
+    ctx.bind(psi, pw.PW_C64)
+    g = ctx.eval_x(xs, 1e-4)
+    ctx.close()
+    del psi
+    torch.cuda.empty_cache()
     psi_m_checks(n, g, xs)
 
 
