@@ -182,8 +182,8 @@ static void reduce_spectrum(const cplx* F, int n, double eps, int max_alpha, xre
     r->gap = gap;
 }
 
-/* Per-family results for a list of x (Algorithm 1 body, lines 3-6 plus the
- * Shannon term).  Outputs are arrays of length nx; m has nx*(max_alpha-1)
+/* Per-family results for a list of x (the per-family steps of Algorithm 1: product,
+ * transform, nullity count and moments, plus the Shannon term).  Outputs are arrays of length nx; m has nx*(max_alpha-1)
  * entries, alpha-major within each x. */
 PWO_EXPORT int pwo_eval_x(int n, const double* psi_in, const uint64_t* xs, int64_t nx, double eps,
                           int max_alpha, double* p, double* ent, double* m, uint64_t* nu, double* gap) {
