@@ -305,7 +305,7 @@ pw_status run_norm(pw_ctx c, double* out) {
 }
 
 // Evaluate nx families whose x are in device memory (or x0 + i when d_xs is null),
-// results to device array d_out.  Chunked by the context batch.
+// results to device array d_out, in launches of the context's launch batch, on st.
 pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
                          hipStream_t st) {
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
