@@ -178,7 +178,9 @@ PW_API pw_status pw_clifford2_table(int* count, double* mats);
 PW_API pw_status pw_eval_x(pw_ctx ctx, const uint64_t* xs, int64_t n_x, double eps, pw_xres* out);
 
 /* Same, with device arrays, enqueued without synchronising (graph-capturable
- * when a workspace is set). */
+ * when a workspace is set).  The list is not checked on the host: each x is
+ * taken modulo 2^n (bits at or above n are ignored, and the result records the
+ * reduced x), so no list makes the kernels read outside the state. */
 PW_API pw_status pw_eval_x_device(pw_ctx ctx, const uint64_t* d_xs, int64_t n_x, double eps, pw_xres* d_out);
 
 /* The signed expectation values c(x, z) = (-i)^{|x&z|} F_x(z) of one family,

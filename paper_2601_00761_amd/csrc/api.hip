@@ -1118,9 +1118,8 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
     if (!(lambda > 0.0 && lambda <= 1.0)) return fail(PW_ERR_ARG, "lambda must be in (0, 1]");
     if (batch < 1 || batch > c->made.maxB) return fail(PW_ERR_ARG, "batch must be in [1, %d]", c->made.maxB);
     if (pilot < 1 || max_samples < 3) return fail(PW_ERR_ARG, "need pilot >= 1 and max_samples >= 3");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
     const int n = c->n;
-    const double d = ldexp(1.0, n);
-    (void)d;
     FamilyRes r0;
     const uint64_t zero = 0;
     s = eval_host(c, &zero, 1, eps, &r0);

@@ -492,7 +492,7 @@ k_fused(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     __shared__ cx<R> lds[Lds<K>::elems];
     __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
     const uint32_t slot = blockIdx.x;
-    const uint64_t x = xs ? xs[slot] : x0 + slot;
+    const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);  // device lists: x mod 2^n
     R re[1 << RL], im[1 << RL];
     load_products<R, TL, RL>(psi, n - 1, (uint32_t)x, 0u, re, im);
     tile_fwht<R, TL, RL, 0>(re, im, lds);
@@ -638,7 +638,7 @@ k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT>::v];
     const int nh = n - 1;
     const uint32_t tile = blockIdx.x, slot = blockIdx.y;
-    const uint32_t x = (uint32_t)(xs ? xs[slot] : x0 + slot);
+    const uint32_t x = (uint32_t)((xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull));
     R re[1 << RL], im[1 << RL];
     if (x >= (1u << K)) load_products_hi<R, TL, RL>(psi, x, tile, re, im);
     else load_products<R, TL, RL>(psi, nh, x, tile, re, im);
@@ -789,7 +789,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
         }
     } else {
         __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
-        const uint64_t x = xs ? xs[slot] : x0 + slot;
+        const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);
         const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
         if (threadIdx.x == 0) parts[(size_t)slot * G + bid] = raw_res(tot, x);
     }

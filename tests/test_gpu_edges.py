@@ -104,3 +104,29 @@ def test_argument_errors_launch_nothing():
     g = ctx.exact(1e-7)
     ctx.close()
     assert g["n_samples"] == 1 << n
+
+
+@pytest.mark.parametrize("n,dtype", [(10, 0), (16, 1), (23, 1)])
+def test_device_list_takes_x_mod_2n(n, dtype):
+    # a device list is not checked on the host: bits of x at or above n are ignored, so
+    # the results equal those of the reduced list (fused, 12-bit and 15-bit plans)
+    import torch
+    eps = 1e-7 if dtype == 0 else 1e-4
+    psi = synth.haar_state(n, 70 + n)
+    ctx = make_ctx(psi, dtype)
+    log("device list mod 2^n n=%d dtype=%d" % (n, dtype))
+    rng = np.random.default_rng(n)
+    k = 40
+    xs = rng.integers(0, 1 << n, size=k, dtype=np.uint64)
+    xs[0] = 0
+    hi = rng.integers(1, 1 << (64 - n), size=k, dtype=np.uint64) << np.uint64(n)
+    d_xs = torch.from_numpy((xs | hi).view(np.int64)).to("cuda:0")
+    d_out = torch.zeros(k * pw.XRES_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+    pw.pw_eval_x_device(ctx.h, d_xs, k, eps, d_out)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy().view(pw.XRES_DTYPE)
+    ref = ctx.eval_x(xs, eps)
+    ctx.close()
+    assert np.array_equal(got["x"], xs)
+    for f in ("p", "ent", "m", "gap", "nu"):
+        assert np.array_equal(got[f], ref[f]), f
