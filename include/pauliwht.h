@@ -190,7 +190,10 @@ PW_API pw_status pw_family_values(pw_ctx ctx, uint64_t x, double* c);
 /* Draw n x-strings on the device (Philox4x32-10 counters keyed by seed; sample i
  * uses counter offset + i) into the host array xs_out.  Marginal sampling draws
  * x = b1 ^ b2 with b1, b2 ~ |psi|^2 by inverse CDF and redraws x = 0 (at most
- * 64 attempts; a sample still 0 is returned as 0). */
+ * 64 attempts; a sample still 0 then takes the pair directly from its law given
+ * b1 != b2: b1 ~ q (T - q), b2 ~ q without b1).  The draws follow
+ * p(x) / (1 - p(0)) on x != 0 exactly for any p(0) < 1; x = 0 is returned only
+ * when |psi|^2 is a point mass. */
 PW_API pw_status pw_sample_x(pw_ctx ctx, pw_sampler sampler, uint64_t seed, uint64_t offset, int64_t n,
                       uint64_t* xs_out);
 

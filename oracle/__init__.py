@@ -55,6 +55,8 @@ def lib():
         L.pwo_sample_marginal_nz.argtypes = [ctypes.c_int, _dp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                              _u64p, _dp]
         L.pwo_sample_marginal_nz.restype = ctypes.c_int64
+        L.pwo_sample_distinct_pairs.argtypes = [ctypes.c_int, _dp, ctypes.c_uint64, ctypes.c_int64, _u64p]
+        L.pwo_sample_distinct_pairs.restype = ctypes.c_int64
         L.pwo_mixed.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp]
         _LIB = L
     return _LIB
@@ -198,11 +200,21 @@ def sample_marginal_nz(psi, seed, offset, count, return_cdf=False):
     a, p = _c128(psi)
     n = _nq(a)
     xs = np.empty(count, dtype=np.uint64)
-    C = np.empty(1 << n)
+    C = np.empty(2 << n)
     failed = _chk(lib().pwo_sample_marginal_nz(n, p, seed, offset, count, xs.ctypes.data_as(_u64p),
                                                C.ctypes.data_as(_dp)))
     if return_cdf:
-        return xs, failed, C
+        return xs, failed, C[:1 << n]
+    return xs, failed
+
+
+def sample_distinct_pairs(psi, seed, count):
+    """x = b1 ^ b2 from the direct law of two independent draws from q = |psi|^2
+    conditioned on b1 != b2 (the sampler's last resort, used alone here)."""
+    a, p = _c128(psi)
+    n = _nq(a)
+    xs = np.empty(count, dtype=np.uint64)
+    failed = _chk(lib().pwo_sample_distinct_pairs(n, p, seed, count, xs.ctypes.data_as(_u64p)))
     return xs, failed
 
 

@@ -403,14 +403,43 @@ PWO_EXPORT int pwo_sample_uniform_nz(int n, uint64_t seed, uint64_t offset, int6
     return 0;
 }
 
-/* Inverse-CDF draw: smallest k with C[k] > t. */
-static uint64_t cdf_search(const double* C, uint64_t d, double t) {
-    uint64_t lo = 0, hi = d - 1;
+/* Inverse-CDF draw restricted to [lo, hi]: smallest k there with C[k] > t, or hi. */
+static uint64_t cdf_search_in(const double* C, uint64_t lo, uint64_t hi, double t) {
     while (lo < hi) {
         uint64_t mid = lo + ((hi - lo) >> 1);
         if (C[mid] > t) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+/* Inverse-CDF draw: smallest k with C[k] > t. */
+static uint64_t cdf_search(const double* C, uint64_t d, double t) { return cdf_search_in(C, 0, d - 1, t); }
+
+/* A pair b1 != b2 drawn directly from the law of two independent draws from q
+ * conditioned on being different: b1 from w(b) = q(b) (T - q(b)) (the chance that b
+ * comes first and the second draw is not b; Cw its inclusive prefix sum), then b2
+ * from q with b1 removed, i.e. the point u2 (T - q(b1)) of the remaining mass mapped
+ * past b1's own interval of C.  Returns b1 ^ b2 (never 0), or 0 when w vanishes
+ * (q a point mass). */
+static uint64_t draw_distinct_pair(const double* C, const double* Cw, uint64_t d, double u1, double u2) {
+    const double T = C[d - 1], Tw = Cw[d - 1];
+    if (!(Tw > 0.0)) return 0;
+    const uint64_t b1 = cdf_search(Cw, d, u1 * Tw);
+    const double B = b1 ? C[b1 - 1] : 0.0;      /* mass below b1 */
+    const double t = u2 * (T - (C[b1] - B));    /* a point of the mass without b1 */
+    uint64_t b2;
+    if (b1 > 0 && (t < B || b1 == d - 1)) b2 = cdf_search_in(C, 0, b1 - 1, t);
+    else b2 = cdf_search_in(C, b1 + 1, d - 1, C[b1] + (t - B));
+    return b1 ^ b2;
+}
+
+/* Inclusive prefix sums of q = |psi|^2 (C) and of w = q (T - q), T = C[d-1] (Cw). */
+static void build_cdfs(const cplx* psi, uint64_t d, double* C, double* Cw) {
+    double run = 0.0;
+    for (uint64_t b = 0; b < d; ++b) { run += cabs2(psi[b]); C[b] = run; }
+    const double T = C[d - 1];
+    run = 0.0;
+    for (uint64_t b = 0; b < d; ++b) { const double q = cabs2(psi[b]); run += q * (T - q); Cw[b] = run; }
 }
 
 /* Draws from the exact x-marginal p(x) = sum_b q(b) q(b^x), conditioned on x != 0:
@@ -419,17 +448,19 @@ static uint64_t cdf_search(const double* C, uint64_t d, double t) {
  * Attempt a of sample i uses Philox(ctr = (offset+i, a, MARG), key = seed):
  * u1 = (W0 >> 11) 2^-53, u2 = (W1 >> 11) 2^-53, b_j = smallest k with
  * C[k] > u_j C[d-1], C the inclusive prefix sum of q.  A sample that is still 0
- * after 64 attempts is returned as 0; the return value counts such samples.
- * Also returns, if C_out is given, the prefix sums used. */
+ * after 64 attempts takes the words of attempt 64 and draw_distinct_pair, which has
+ * the same conditional law, so the output law is exact whatever p(0) < 1.  The
+ * return value counts samples left at 0 (only when q is a point mass).  Also
+ * returns, if C_out is given, the prefix sums used (C_out[0..d): C; C_out[d..2d): Cw). */
 PWO_EXPORT int64_t pwo_sample_marginal_nz(int n, const double* psi_in, uint64_t seed, uint64_t offset,
                                           int64_t count, uint64_t* xs, double* C_out) {
     if (n < 1 || n > 30 || count < 0 || !xs || !psi_in) return -1;
     const uint64_t d = 1ull << n;
     const cplx* psi = (const cplx*)psi_in;
-    double* C = C_out ? C_out : (double*)malloc(sizeof(double) * d);
+    double* C = C_out ? C_out : (double*)malloc(sizeof(double) * 2 * d);
     if (!C) return -2;
-    double run = 0.0;
-    for (uint64_t b = 0; b < d; ++b) { run += cabs2(psi[b]); C[b] = run; }
+    double* Cw = C + d;
+    build_cdfs(psi, d, C, Cw);
     const double T = C[d - 1];
     int64_t failed = 0;
     for (int64_t i = 0; i < count; ++i) {
@@ -441,10 +472,35 @@ PWO_EXPORT int64_t pwo_sample_marginal_nz(int n, const double* psi_in, uint64_t 
             uint64_t b1 = cdf_search(C, d, u1 * T), b2 = cdf_search(C, d, u2 * T);
             x = b1 ^ b2;
         }
+        if (x == 0) {
+            uint64_t W0, W1;
+            philox_words(seed, offset + (uint64_t)i, PWO_MAX_ATTEMPTS, PWO_STREAM_MARGINAL, &W0, &W1);
+            x = draw_distinct_pair(C, Cw, d, (double)(W0 >> 11) * 0x1.0p-53, (double)(W1 >> 11) * 0x1.0p-53);
+        }
         if (x == 0) ++failed;
         xs[i] = x;
     }
     if (!C_out) free(C);
+    return failed;
+}
+
+/* The direct distinct-pair law alone (the words of attempt 64 for every sample), so
+ * that tests can pin it on states where the redraw loop would rarely reach it.
+ * Returns the number of samples left at 0. */
+PWO_EXPORT int64_t pwo_sample_distinct_pairs(int n, const double* psi_in, uint64_t seed, int64_t count, uint64_t* xs) {
+    if (n < 1 || n > 30 || count < 0 || !xs || !psi_in) return -1;
+    const uint64_t d = 1ull << n;
+    double* C = (double*)malloc(sizeof(double) * 2 * d);
+    if (!C) return -2;
+    build_cdfs((const cplx*)psi_in, d, C, C + d);
+    int64_t failed = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        uint64_t W0, W1;
+        philox_words(seed, (uint64_t)i, PWO_MAX_ATTEMPTS, PWO_STREAM_MARGINAL, &W0, &W1);
+        xs[i] = draw_distinct_pair(C, C + d, d, (double)(W0 >> 11) * 0x1.0p-53, (double)(W1 >> 11) * 0x1.0p-53);
+        if (xs[i] == 0) ++failed;
+    }
+    free(C);
     return failed;
 }
 

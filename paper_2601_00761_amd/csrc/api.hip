@@ -102,10 +102,10 @@ Layout layout_for(int n, pw_dtype dt, int batch) {
     off += align256((size_t)chunk * sizeof(FamilyRes));
     L.sweep = off;
     off += align256((size_t)(SWEEP_SLOTS + 1) * sizeof(SweepSums));
-    L.cdf = off;
-    off += align256(((size_t)1 << n) * sizeof(double));
+    L.cdf = off;   // marginal-sampler tables: prefix sums of q, then of q (T - q)
+    off += align256(((size_t)2 << n) * sizeof(double));
     L.cdfblk = off;
-    off += align256(cdf_blk_elems(n) * sizeof(double));
+    off += align256(2 * cdf_blk_elems(n) * sizeof(double));
     L.norm = off;
     off += align256((size_t)(norm2_parts(n) + 2) * sizeof(double));
     L.ctr = off;
@@ -822,12 +822,12 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
             s = pw_sample_x(c, sampler, seed, drawn, nb, xs.data());
             if (s != PW_OK) return s;
             for (int64_t i = 0; i < nb; ++i)
-                if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
+                if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "the marginal sampler drew x = 0 (|psi|^2 is a point mass)");
             s = eval_host(c, xs.data(), nb, eps, res.data());
             if (s != PW_OK) return s;
         }
         for (int64_t i = 0; i < nb; ++i) {
-            if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
+            if (xs[i] == 0) return fail(PW_ERR_UNSUPPORTED, "the marginal sampler drew x = 0 (|psi|^2 is a point mass)");
             const FamilyRes& f = res[i];
             const double w = sampler == PW_SAMPLER_UNIFORM_NZ ? (d - 1.0) : (1.0 - p0) / f.p;
             for (int a = 0; a < 3; ++a) run[a].add(w * f.m[a]);
@@ -1132,7 +1132,7 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
     s = pw_sample_x(c, PW_SAMPLER_MARGINAL_NZ, seed, 0, pilot, px.data());
     if (s != PW_OK) return s;
     for (int64_t i = 0; i < pilot; ++i)
-        if (px[i] == 0) return fail(PW_ERR_UNSUPPORTED, "marginal sampler could not draw x != 0 in 64 attempts");
+        if (px[i] == 0) return fail(PW_ERR_UNSUPPORTED, "the marginal sampler drew x = 0 (|psi|^2 is a point mass)");
     s = eval_host(c, px.data(), pilot, eps, pr.data());
     if (s != PW_OK) return s;
     std::vector<double> pw_((size_t)pilot);

@@ -3,7 +3,10 @@
 //  * Uniform over F_2^N \ {0} (the paper's Monte Carlo section).
 //  * Exact x-marginal p(x) = sum_z c_{x,z}^2 / d = sum_b q(b) q(b^x), q = |psi|^2:
 //    x = b1 ^ b2 with b1, b2 independent draws from q, redrawn while x = 0.
-//    Draws from q invert an FP64 inclusive prefix sum of q.
+//    Draws from q invert an FP64 inclusive prefix sum of q.  A draw still 0 after
+//    64 attempts takes the pair directly from its law given b1 != b2 (b1 from
+//    q (T - q), a second prefix sum, then b2 from q without b1), so the output
+//    follows p(x) / (1 - p(0)) exactly whatever p(0) < 1.
 //
 // Random words come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
 // counter (i_lo, i_hi, attempt, stream) and key (seed_lo, seed_hi), so the
@@ -32,20 +35,29 @@ __global__ void k_uniform(int n, uint64_t seed, uint64_t offset, const uint64_t*
     xs[i] = 1ull + __umul64hi(W0, (1ull << n) - 1ull);
 }
 
-// Phase 1: fixed-order sum of q over each chunk.
-template <typename R>
-__global__ void __launch_bounds__(256) k_cdf_sums(const cx<R>* __restrict__ psi, uint64_t d, double* __restrict__ blk) {
+// The weight summed into a prefix table: q(b) = |psi(b)|^2, or with W the weight
+// q(b) (T - q(b)) of b as the first element of a pair of distinct draws, T the total
+// of q (the last entry of the finished q table).
+template <typename R, bool W>
+__device__ __forceinline__ double cdf_weight(const cx<R>* __restrict__ psi, uint64_t b, const double* __restrict__ qtot) {
+    const cx<R> v = psi[b];
+    const double re = (double)v.re, im = (double)v.im;
+    const double q = re * re + im * im;
+    if constexpr (W) return q * (*qtot - q);
+    return q;
+}
+
+// Phase 1: fixed-order sum of the weights over each chunk.
+template <typename R, bool W>
+__global__ void __launch_bounds__(256) k_cdf_sums(const cx<R>* __restrict__ psi, uint64_t d, double* __restrict__ blk,
+                                                  const double* __restrict__ qtot) {
     __shared__ double sh[256];
     const uint64_t base = (uint64_t)blockIdx.x * CDF_CHUNK;
     double s = 0.0;
     // thread t owns the 16 consecutive amplitudes [base + 16t, base + 16t + 16)
     for (int j = 0; j < CDF_CHUNK / 256; ++j) {
         const uint64_t b = base + (uint64_t)threadIdx.x * (CDF_CHUNK / 256) + j;
-        if (b < d) {
-            const cx<R> v = psi[b];
-            const double re = (double)v.re, im = (double)v.im;
-            s += re * re + im * im;
-        }
+        if (b < d) s += cdf_weight<R, W>(psi, b, qtot);
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -85,9 +97,10 @@ __global__ void __launch_bounds__(256) k_cdf_scan_blocks(double* __restrict__ bl
 }
 
 // Phase 3: inclusive scan inside each chunk plus the chunk's offset.
-template <typename R>
+template <typename R, bool W>
 __global__ void __launch_bounds__(256)
-k_cdf_final(const cx<R>* __restrict__ psi, uint64_t d, const double* __restrict__ blk, double* __restrict__ cdf) {
+k_cdf_final(const cx<R>* __restrict__ psi, uint64_t d, const double* __restrict__ blk, double* __restrict__ cdf,
+            const double* __restrict__ qtot) {
     __shared__ double sh[256];
     constexpr int PER = CDF_CHUNK / 256;
     const uint64_t base = (uint64_t)blockIdx.x * CDF_CHUNK + (uint64_t)threadIdx.x * PER;
@@ -96,13 +109,7 @@ k_cdf_final(const cx<R>* __restrict__ psi, uint64_t d, const double* __restrict_
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const uint64_t b = base + j;
-        double v = 0.0;
-        if (b < d) {
-            const cx<R> a = psi[b];
-            const double re = (double)a.re, im = (double)a.im;
-            v = re * re + im * im;
-        }
-        s += v;
+        s += b < d ? cdf_weight<R, W>(psi, b, qtot) : 0.0;
         q[j] = s;
     }
     const double inc = block_incl_scan(s, sh);
@@ -114,14 +121,30 @@ k_cdf_final(const cx<R>* __restrict__ psi, uint64_t d, const double* __restrict_
     }
 }
 
-__device__ __forceinline__ uint64_t upper_bound(const double* __restrict__ C, uint64_t d, double t) {
-    uint64_t lo = 0, hi = d - 1;
+// Smallest k in [lo, hi] with C[k] > t, or hi when there is none.
+__device__ __forceinline__ uint64_t upper_bound(const double* __restrict__ C, uint64_t lo, uint64_t hi, double t) {
     while (lo < hi) {
         const uint64_t mid = lo + ((hi - lo) >> 1);
         if (C[mid] > t) hi = mid;
         else lo = mid + 1;
     }
     return lo;
+}
+
+// b1 from the table of q (T - q), then b2 from q with b1's own interval of C taken
+// out: the point u2 (T - q(b1)) of the remaining mass, searched below b1 or, shifted
+// past b1's interval, above it.  b2 != b1 by construction; 0 only when the q (T - q)
+// table is empty (q a point mass).
+__device__ __forceinline__ uint64_t distinct_pair(const double* __restrict__ C, const double* __restrict__ Cw,
+                                                  uint64_t d, double u1, double u2) {
+    const double T = C[d - 1], Tw = Cw[d - 1];
+    if (!(Tw > 0.0)) return 0;
+    const uint64_t b1 = upper_bound(Cw, 0, d - 1, u1 * Tw);
+    const double below = b1 ? C[b1 - 1] : 0.0;
+    const double t = u2 * (T - (C[b1] - below));
+    const uint64_t b2 = (b1 > 0 && (t < below || b1 == d - 1)) ? upper_bound(C, 0, b1 - 1, t)
+                                                                : upper_bound(C, b1 + 1, d - 1, C[b1] + (t - below));
+    return b1 ^ b2;
 }
 
 __global__ void k_marginal(int n, const double* __restrict__ cdf, uint64_t seed, uint64_t offset,
@@ -136,7 +159,12 @@ __global__ void k_marginal(int n, const double* __restrict__ cdf, uint64_t seed,
         uint64_t W0, W1;
         words(seed, offset + (uint64_t)i, (uint32_t)a, STREAM_MARGINAL, W0, W1);
         const double u1 = (double)(W0 >> 11) * 0x1.0p-53, u2 = (double)(W1 >> 11) * 0x1.0p-53;
-        x = upper_bound(cdf, d, u1 * T) ^ upper_bound(cdf, d, u2 * T);
+        x = upper_bound(cdf, 0, d - 1, u1 * T) ^ upper_bound(cdf, 0, d - 1, u2 * T);
+    }
+    if (x == 0) {
+        uint64_t W0, W1;
+        words(seed, offset + (uint64_t)i, (uint32_t)MAX_ATTEMPTS, STREAM_MARGINAL, W0, W1);
+        x = distinct_pair(cdf, cdf + d, d, (double)(W0 >> 11) * 0x1.0p-53, (double)(W1 >> 11) * 0x1.0p-53);
     }
     xs[i] = x;
 }
@@ -165,23 +193,33 @@ size_t cdf_blk_elems(int n) {
     return (size_t)((d + CDF_CHUNK - 1) / CDF_CHUNK);
 }
 
-hipError_t build_cdf(bool dbl, const void* psi, int n, double* d_cdf, double* d_blk, hipStream_t st) {
-    const uint64_t d = 1ull << n;
-    const unsigned nb = (unsigned)cdf_blk_elems(n);
-    if (dbl)
-        hipLaunchKernelGGL(k_cdf_sums<double>, dim3(nb), dim3(256), 0, st, (const cx<double>*)psi, d, d_blk);
-    else
-        hipLaunchKernelGGL(k_cdf_sums<float>, dim3(nb), dim3(256), 0, st, (const cx<float>*)psi, d, d_blk);
+template <typename R, bool W>
+hipError_t build_table(const cx<R>* psi, uint64_t d, unsigned nb, double* tab, double* blk, const double* qtot,
+                       hipStream_t st) {
+    hipLaunchKernelGGL((k_cdf_sums<R, W>), dim3(nb), dim3(256), 0, st, psi, d, blk, qtot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cdf_scan_blocks, dim3(1), dim3(256), 0, st, d_blk, (int64_t)nb);
+    hipLaunchKernelGGL(k_cdf_scan_blocks, dim3(1), dim3(256), 0, st, blk, (int64_t)nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (dbl)
-        hipLaunchKernelGGL(k_cdf_final<double>, dim3(nb), dim3(256), 0, st, (const cx<double>*)psi, d, d_blk, d_cdf);
-    else
-        hipLaunchKernelGGL(k_cdf_final<float>, dim3(nb), dim3(256), 0, st, (const cx<float>*)psi, d, d_blk, d_cdf);
+    hipLaunchKernelGGL((k_cdf_final<R, W>), dim3(nb), dim3(256), 0, st, psi, d, blk, tab, qtot);
     return hipGetLastError();
+}
+
+template <typename R>
+hipError_t build_tables(const cx<R>* psi, int n, double* d_cdf, double* d_blk, hipStream_t st) {
+    const uint64_t d = 1ull << n;
+    const unsigned nb = (unsigned)cdf_blk_elems(n);
+    hipError_t e = build_table<R, false>(psi, d, nb, d_cdf, d_blk, nullptr, st);
+    if (e != hipSuccess) return e;
+    return build_table<R, true>(psi, d, nb, d_cdf + d, d_blk + nb, d_cdf + (d - 1), st);
+}
+
+// d_cdf holds 2 * 2^n doubles (the prefix sums of q = |psi|^2, then those of
+// q (T - q)), d_blk 2 * cdf_blk_elems(n) doubles of chunk offsets.
+hipError_t build_cdf(bool dbl, const void* psi, int n, double* d_cdf, double* d_blk, hipStream_t st) {
+    return dbl ? build_tables((const cx<double>*)psi, n, d_cdf, d_blk, st)
+               : build_tables((const cx<float>*)psi, n, d_cdf, d_blk, st);
 }
 
 hipError_t sample_marginal(int n, const double* d_cdf, uint64_t seed, uint64_t offset, int64_t count, uint64_t* d_xs,

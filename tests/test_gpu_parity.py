@@ -291,6 +291,50 @@ def test_mc_marginal_matches_oracle_on_same_list():
     assert abs(res["M_se"][0] / sM - 1) < 1e-8
 
 
+def _x0_dominated_state(n, delta, seed):
+    # sqrt(1-delta)|0> + sqrt(delta)|Haar>: p(0) ~ 1 - 2 delta, so most marginal draws
+    # stay 0 through the 64 redraws and take the direct distinct-pair law
+    psi = np.sqrt(delta) * synth.haar_state(n, seed)
+    psi[0] += np.sqrt(1 - delta)
+    return psi / np.linalg.norm(psi)
+
+
+@pytest.mark.parametrize("n,dtype", [(12, 0), (16, 1)])
+def test_marginal_sampler_fallback_matches_oracle(n, dtype):
+    psi = as_input(_x0_dominated_state(n, 0.0005, 710 + n), dtype)
+    ctx = make_ctx(psi, dtype)
+    log("marginal sampler, x = 0 dominated, n=%d" % n)
+    g = ctx.sample_x(pw.PW_SAMPLER_MARGINAL_NZ, 78, 3, 3000)
+    ctx.close()
+    r, failed = oracle.sample_marginal_nz(psi, 78, 3, 3000)
+    assert failed == 0 and np.all(g > 0)
+    mism = np.nonzero(g != r)[0]
+    assert len(mism) <= 2, mism
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_mc_marginal_x0_dominated_matches_oracle(graphs):
+    # p(0) ~ 0.999: the Monte Carlo call completes (no draw is left at 0) and equals
+    # the oracle's estimator on the same list, eager and with graph replay
+    n = 14
+    psi = _x0_dominated_state(n, 0.0005, 905)
+    ctx = make_ctx(psi, pw.PW_C128)
+    pw.pw_set_graphs(ctx.h, graphs)
+    log("mc marginal x0-dominated graphs=%d" % graphs)
+    res = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-7, 32, 97, 0.0, 98)
+    xs = ctx.sample_x(pw.PW_SAMPLER_MARGINAL_NZ, 98, 0, 96)
+    ctx.close()
+    r_xs, failed = oracle.sample_marginal_nz(psi, 98, 0, 96)
+    assert failed == 0 and np.count_nonzero(xs != r_xs) <= 1
+    allx = np.concatenate([[0], xs]).astype(np.uint64)
+    r = oracle.eval_x(psi, allx)
+    assert r["p"][0] > 0.998
+    S, se, sM = oracle.mc_marginal(r["m"][0, 0], r["p"][0], r["m"][1:, 0], r["p"][1:], 2)
+    assert res["n_samples"] == 97
+    assert abs(res["S"][0] / S - 1) < 1e-10
+    assert abs(res["M_se"][0] / sM - 1) < 1e-8
+
+
 def test_errors_reported():
     n = 10
     psi = synth.haar_state(n, 1)

@@ -247,6 +247,80 @@ def test_marginal_sampler_chi2_against_exact_table():
     assert chi2 < dof + 6 * math.sqrt(2 * dof)
 
 
+@pytest.mark.parametrize("delta", [0.015, 0.0005])
+def test_marginal_sampler_exact_when_x0_dominates(delta):
+    # psi = sqrt(1-delta)|0> + sqrt(delta)|phi>: p(0) ~ 0.97 (14 % of the draws still 0
+    # after 64 attempts) or ~ 0.999 (94 %); those draws come from the direct law of a
+    # distinct pair, and the whole output must follow p(x)/(1 - p(0)) on x != 0
+    n = 6
+    phi = synth.haar_state(n, 83)
+    psi = np.sqrt(delta) * phi
+    psi[0] += np.sqrt(1 - delta)
+    psi /= np.linalg.norm(psi)
+    p = oracle.marginal(psi, np.arange(1 << n, dtype=np.uint64))
+    assert p[0] > (0.96 if delta > 0.001 else 0.998)
+    xs, failed = oracle.sample_marginal_nz(psi, 123, 0, 100000)
+    assert failed == 0 and xs.min() >= 1
+    e = len(xs) * p[1:] / (1 - p[0])
+    cnt = np.bincount(xs.astype(np.int64), minlength=1 << n)[1:]
+    chi2 = np.sum((cnt - e) ** 2 / e)
+    dof = (1 << n) - 2
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
+def test_distinct_pair_law_alone():
+    # the direct law on a state with two heavy basis states (q = 0.3 each) and the
+    # rest spread: the frequency of x = h1 ^ h2 is 2 q1 q2 / (1 - sum q^2), which a
+    # first element drawn from q instead of q (1 - q) would inflate by ~17 %
+    n = 6
+    rng = np.random.default_rng(5)
+    q = rng.uniform(0.5, 1.5, 1 << n)
+    q[[3, 44]] = 0
+    q *= 0.4 / q.sum()
+    q[[3, 44]] = 0.3
+    psi = np.sqrt(q) * np.exp(2j * np.pi * rng.uniform(size=1 << n))
+    p = oracle.marginal(psi, np.arange(1 << n, dtype=np.uint64))
+    xs, failed = oracle.sample_distinct_pairs(psi, 31, 100000)
+    assert failed == 0 and xs.min() >= 1
+    e = len(xs) * p[1:] / (1 - p[0])
+    cnt = np.bincount(xs.astype(np.int64), minlength=1 << n)[1:]
+    chi2 = np.sum((cnt - e) ** 2 / e)
+    dof = (1 << n) - 2
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+    k = 3 ^ 44
+    assert abs(cnt[k - 1] - e[k - 1]) < 5 * math.sqrt(e[k - 1])
+
+
+def test_marginal_sampler_sparse_support_and_point_mass():
+    # q on four basis states, one of them dominant: every draw is a difference of two
+    # distinct support points, with the exact conditional frequencies; a point mass
+    # leaves every draw at 0 (the sampler reports them as failed)
+    n = 6
+    sup = [0, 5, 17, 40]
+    amp = np.array([np.sqrt(0.994), 0.05, 0.05j, -np.sqrt(1 - 0.994 - 0.005)])
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[sup] = amp
+    q = np.abs(psi) ** 2
+    xs, failed = oracle.sample_marginal_nz(psi, 7, 0, 60000)
+    assert failed == 0
+    pairs = {}
+    for a in sup:
+        for b in sup:
+            if a != b:
+                pairs[a ^ b] = pairs.get(a ^ b, 0.0) + q[a] * q[b]
+    tot = sum(pairs.values())
+    vals, cnt = np.unique(xs, return_counts=True)
+    assert set(int(v) for v in vals) <= set(pairs)
+    e = np.array([len(xs) * pairs[k] / tot for k in sorted(pairs)])
+    c = np.array([dict(zip(vals.tolist(), cnt.tolist())).get(k, 0) for k in sorted(pairs)])
+    dof = len(pairs) - 1
+    assert np.sum((c - e) ** 2 / e) < dof + 6 * math.sqrt(2 * dof)
+    basis = np.zeros(1 << n, dtype=np.complex128)
+    basis[9] = 1
+    xs0, failed0 = oracle.sample_marginal_nz(basis, 7, 0, 50)
+    assert failed0 == 50 and not xs0.any()
+
+
 # --------------------------------------------------------------------------- estimators
 
 def test_uniform_estimator_is_unbiased():
