@@ -76,6 +76,23 @@ def load_traffic(kernel, summary="pmc_traffic_c64_n20.json"):
     return k.get("hbm_bytes_per_launch")
 
 
+def fill_ceiling(torch, nbytes=256 << 20, reps=20):
+    """GB/s of a plain fill of nbytes (torch fill_, timed with events on torch's stream):
+    the write ceiling of the memory fabric for one launch's worth of half spectra."""
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        buf.fill_(1.0)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(reps):
+        buf.fill_(float(i))
+    b.record()
+    b.synchronize()
+    gbps = nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del buf
+    return gbps
+
+
 def prepare_state(pw, torch, n, seed):
     import numpy as np
     import synth
@@ -440,6 +457,12 @@ def main():
         roofline["traffic_GBps"] = round(traffic / (d["avg_ms"] * 1e-3) / 1e9, 1)
         roofline["traffic_note"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch (L2 <-> fabric: MALL or HBM) "
                                     "over the HIP-event duration")
+    if traffic is not None and dom == 1:
+        # what bounds the first pass in practice: the fabric's write rate for the batch's
+        # half spectra, measured here by a plain fill of the same size
+        fill = fill_ceiling(torch, int(d["families_per_launch"] * half_points * 8))
+        roofline["fill_ceiling"] = {"GBps": round(fill, 1), "traffic_frac": round(roofline["traffic_GBps"] / fill, 4),
+                                    "note": "plain fill (torch fill_) of the bytes the launch writes, same GPU"}
 
     el128 = r128 = None
     if args.steps_c128 > 0:
