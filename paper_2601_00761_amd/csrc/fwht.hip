@@ -106,7 +106,9 @@ __device__ __forceinline__ void reg_stages(R (&re)[1 << RL], R (&im)[1 << RL]) {
 // Move the points from window AO to window AN through LDS.  The address of
 // (thread t, register j) in window A is pad(T_A(t) | j 2^A) = pad(T_A(t)) + pad(j 2^A)
 // (the two parts have disjoint bits), i.e. a per-thread base plus a constant.
-template <typename R, int TL, int RL, int AO, int AN>
+// TRAIL: end with a barrier, needed only when the same buffer is written again
+// before every thread has passed another barrier.
+template <typename R, int TL, int RL, int AO, int AN, bool TRAIL = true>
 __device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<R>* lds) {
     const uint32_t tid = threadIdx.x;
     cx<R>* wo = lds + padi(thread_part<AO, RL>(tid));
@@ -125,7 +127,7 @@ __device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<
         re[j] = v.re;
         im[j] = v.im;
     }
-    __syncthreads();
+    if constexpr (TRAIL) __syncthreads();
 }
 
 // The same move for tiles too large for one complex LDS buffer (2^15 single-
@@ -137,7 +139,7 @@ __device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<
 template <int RL>
 __host__ __device__ constexpr uint32_t pads(uint32_t i) { return i + (i >> RL); }
 
-template <typename R, int TL, int RL, int AO, int AN>
+template <typename R, int TL, int RL, int AO, int AN, bool TRAIL = true>
 __device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL], R* buf) {
     static_assert(RL >= 5, "the split buffer is sized for one pad element in 32 or fewer");
     const uint32_t tid = threadIdx.x;
@@ -154,7 +156,7 @@ __device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) im[j] = rn[pads<RL>((uint32_t)j << AN)];
-    __syncthreads();
+    if constexpr (TRAIL) __syncthreads();
 }
 
 // LDS bytes of a tile of 2^K points.
@@ -176,26 +178,29 @@ constexpr int final_window() {
     return b0;
 }
 
-template <typename R, int TL, int RL, int A, int B0, bool SPLIT>
+// REUSE: the workgroup runs another transform through the same buffer afterwards, so
+// every exchange closes with a barrier; otherwise the last one needs none.
+template <typename R, int TL, int RL, int A, int B0, bool SPLIT, bool REUSE>
 struct Rounds {
     static __device__ __forceinline__ void run(R (&re)[1 << RL], R (&im)[1 << RL], void* lds) {
         if constexpr (B0 < TL) {
-            if constexpr (SPLIT) exchange_split<R, TL, RL, A, B0>(re, im, (R*)lds);
-            else exchange<R, TL, RL, A, B0>(re, im, (cx<R>*)lds);
+            constexpr bool trail = REUSE || B0 + RL < TL;
+            if constexpr (SPLIT) exchange_split<R, TL, RL, A, B0, trail>(re, im, (R*)lds);
+            else exchange<R, TL, RL, A, B0, trail>(re, im, (cx<R>*)lds);
             constexpr int B1 = (B0 + RL < TL) ? B0 + RL : TL;
             reg_stages<R, RL, 0, B1 - B0>(re, im);
-            Rounds<R, TL, RL, B0, B0 + RL, SPLIT>::run(re, im, lds);
+            Rounds<R, TL, RL, B0, B0 + RL, SPLIT, REUSE>::run(re, im, lds);
         }
     }
 };
 
 // Unnormalised WHT over bits [LO, K) of the tile index.  On entry thread t holds
 // points t + j 2^TL (window TL); on exit the points are in final_window().
-template <typename R, int TL, int RL, int LO, bool SPLIT = false>
+template <typename R, int TL, int RL, int LO, bool SPLIT = false, bool REUSE = false>
 __device__ __forceinline__ void tile_fwht(R (&re)[1 << RL], R (&im)[1 << RL], void* lds) {
     constexpr int S0 = LO > TL ? LO : TL;
     reg_stages<R, RL, S0 - TL, RL>(re, im);
-    Rounds<R, TL, RL, TL, LO, SPLIT>::run(re, im, lds);
+    Rounds<R, TL, RL, TL, LO, SPLIT, REUSE>::run(re, im, lds);
 }
 
 // f values of the half-size problem at half indices (tile << K) + t + j 2^TL
@@ -729,7 +734,7 @@ k_first_shared(const cx<R>* __restrict__ psi, int n, uint64_t x0, int fam, cx<R>
             re[j] = ur[j] * vr[j] + ui[j] * vi[j];
             im[j] = ur[j] * vi[j] - ui[j] * vr[j];
         }
-        tile_fwht<R, TL, RL, 0>(re, im, lds);
+        tile_fwht<R, TL, RL, 0, false, true>(re, im, lds);
         store_tile<R, TL, RL>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
         if (k + 1 < fam) {
             switch (__builtin_ctz((unsigned)(k + 1))) {
