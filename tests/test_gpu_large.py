@@ -132,3 +132,39 @@ def test_haar_large_sampled_families_vs_oracle(n, dtype):
             assert abs(g["p"][i] - r["p"][i]) <= b["p"]
             assert abs(g["ent"][i] - r["ent"][i]) <= b["ent"]
         assert int(g["nu"][i]) == int(r["nu"][i])
+
+
+def test_benchmark_sweep_equals_sum_of_families():
+    # the benchmark's workload (N = 20 T-doped Clifford state, eta = 20, N_T = 20,
+    # complex64) swept in the benchmark's launch configuration (default workspace: 64
+    # families per launch, first pass shared over runs of 16) equals the FP64 sum of the
+    # per-family values of all 2^20 x evaluated as one list (unshared first pass);
+    # sampled families agree with the oracle within the FP32 bounds, and the sweep obeys
+    # Parseval (sum_x p(x) = 1) with a power-of-two nullity count
+    n = 20
+    k, q, m = synth.gates_to_arrays(synth.tdoped_stream(n, 20, 20, synth.SEED_BASE + 2))
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1
+    psi = oracle.apply_gates(psi0, k, q, m).astype(np.complex64).astype(np.complex128)
+    log("benchmark sweep n=%d vs family sum" % n)
+    ctx = pw.Context(0)
+    ctx.upload(psi, pw.PW_C64)
+    ex = ctx.exact(1e-4)
+    fams = ctx.eval_x(np.arange(1 << n, dtype=np.uint64), 1e-4)
+    ctx.close()
+    assert ex["n_samples"] == 1 << n
+    for a in range(3):
+        s = math.fsum(fams["m"][:, a])
+        assert abs(ex["S"][a] / s - 1) < 1e-6, (a, ex["S"][a], s)
+    assert abs(ex["L"] / math.fsum(fams["ent"]) - 1) < 1e-6
+    assert abs(ex["P"] - 1) < 1e-5 and abs(math.fsum(fams["p"]) - 1) < 1e-5
+    assert ex["nu_cnt"] == int(fams["nu"].sum()) and ex["nu_cnt"] & (ex["nu_cnt"] - 1) == 0
+    xs = np.array([0, 1, 777, 123456, (1 << n) - 1], dtype=np.uint64)
+    r = oracle.eval_x(psi, xs, eps=1e-4, max_alpha=4)
+    for i, x in enumerate(xs):
+        b = family_bounds(oracle.spectrum(psi, int(x)), n)
+        g = fams[int(x)]
+        assert abs(g["m"][0] - r["m"][i, 0]) <= b["m2"]
+        assert abs(g["p"] - r["p"][i]) <= b["p"]
+        assert abs(g["ent"] - r["ent"][i]) <= b["ent"]
+        assert int(g["nu"]) == int(r["nu"][i])
