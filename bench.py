@@ -205,6 +205,59 @@ def mc_leg(pw, torch, stream, eta, timing_every):
                                  "rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per family of the first and reducing passes"}}
 
 
+MIXED_N = 24
+FP32_PEAK_TFLOPS = 157.3     # published dense FP32 rate (an FMA counts as two)
+FP64_PEAK_TFLOPS = 78.6
+
+
+def mixed_leg(pw, torch, stream):
+    """Mixed-state SRE of the first n_a qubits (Supplemental Material, mixed states,
+    Eq. Msre-mixed) of an N = 24 T-doped Clifford state (eta = 4, N_T = 2N, from
+    |0...0>): rho_A on the device, then all 2^{n_a} x_A families through the partial
+    FWHT.  complex64 with n_a = 14 and complex128 with n_a = 13 (the library's limits).
+    The dominant kernel forms rho_A: its algorithmic work is the Hermitian half,
+    d_A (d_A + 1) / 2 entries of d_E complex multiply-adds (8 flops each)."""
+    import numpy as np
+    import synth
+    n = MIXED_N
+    seed = synth.SEED_BASE + 5
+    kinds, qubits, mats = synth.gates_to_arrays(synth.tdoped_stream(n, 4, 2 * n, seed))
+    out = []
+    for dtype, na, peak in ((pw.PW_C64, 14, FP32_PEAK_TFLOPS), (pw.PW_C128, 13, FP64_PEAK_TFLOPS)):
+        psi0 = np.zeros(1 << n, dtype=np.complex64 if dtype == pw.PW_C64 else np.complex128)
+        psi0[0] = 1.0
+        ctx = pw.Context(0, stream)
+        ctx.upload(psi0, dtype)
+        ctx.apply_gates(kinds, qubits, mats)
+        pw.pw_mixed(ctx.h, na, 1e-4)
+        pw.pw_timing_enable(ctx.h, 1)
+        pw.pw_timing_reset(ctx.h)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = pw.pw_mixed(ctx.h, na, 1e-4 if dtype == pw.PW_C64 else 1e-7)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        cnt, ms, _ = pw.pw_timing_read(ctx.h, 4)
+        pw.pw_timing_enable(ctx.h, 0)
+        ctx.close()
+        rho_us = 1e3 * ms / cnt
+        dA, dE = float(1 << na), float(1 << (n - na))
+        flops = 8.0 * dE * dA * (dA + 1) / 2
+        achieved = flops / (rho_us * 1e-6) / 1e12
+        out.append({"dtype": "f32" if dtype == pw.PW_C64 else "f64", "n_a": na, "seconds_per_call": dt,
+                    "pauli_strings_on_A_per_s": 4.0 ** na / dt, "rho_us": round(rho_us, 1),
+                    "families_us": round(dt * 1e6 - rho_us, 1),
+                    "M2": r["M"][0], "S2": r["S2"], "purity": r["purity"],
+                    "roofline": {"bound": "alu", "kernel": "k_rho", "achieved": round(achieved, 2), "peak": peak,
+                                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                                 "algorithmic_flops_per_launch": flops}})
+    return {"workload": "mixed-state SRE of the first n_a qubits of an N=%d T-doped Clifford state (eta=4, N_T=%d), "
+                        "all 4^n_a Pauli strings on A; rho_A on the device then every x_A family" % (n, 2 * n),
+            "legs": out}
+
+
 MULTI_STATES = 64
 MULTI_X = 64
 
@@ -361,6 +414,8 @@ def main():
                     help="families per launch (0: the library default for the state size)")
     ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=None,
                     help="also run the N=30 learned-vs-plain proposal comparison (minutes; off by default)")
+    ap.add_argument("--mixed-leg", action="store_true",
+                    help="add the mixed-state leg (N=24, n_a = 14 / 13, complex64 / complex128)")
     ap.add_argument("--multistate-leg", action="store_true",
                     help="also run the 64-state uneven-N batch (minute-scale; off by default)")
     ap.add_argument("--learned-draws", type=int, default=2048)
@@ -498,6 +553,8 @@ def main():
         out["m2_wall_time"] = [mc_leg(pw, torch, stream, eta, args.timing_every) for eta in args.mc_eta]
     if args.multistate_leg:
         out["multi_state"] = multistate_leg(pw, torch, stream)
+    if args.mixed_leg:
+        out["mixed_state"] = mixed_leg(pw, torch, stream)
     if args.learned_leg is not None:
         kinds = args.learned_leg or ["psi_m", "tdoped"]
         out["learned_vs_plain"] = [learned_leg(pw, torch, stream, k, args.learned_draws, args.learned_pilot)

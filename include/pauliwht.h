@@ -258,8 +258,9 @@ PW_API pw_status pw_mc_learned(pw_ctx ctx, double eps, int batch, uint64_t max_s
  * (Supplemental Material, mixed states, Eq. Msre-mixed):
  *   M_alpha(rho_A) = log2(W_alpha)/(1 - alpha) - n_a - S_2(rho_A),
  *   W_alpha = sum_{P on A} |Tr(rho_A P)|^{2 alpha} / d_A^alpha,  S_2 = -log2 Tr rho_A^2.
- * rho_A = Psi Psi^dagger (Psi[a, e] = psi(a + 2^{n_a} e)) is formed on the device,
- * then every x_A family is the n_a-bit WHT of h(a) = rho_A[a ^ x_A, a].  1 <= n_a <=
+ * rho_A = Psi Psi^dagger (Psi[a, e] = psi(a + 2^{n_a} e)) is formed on the device
+ * (its 64 x 64 tiles on and above the diagonal: it is Hermitian), then every x_A
+ * family is the n_a-bit WHT of h(a) = rho_A[a ^ x_A, a].  1 <= n_a <=
  * min(n, 14 (c64) / 13 (c128)); rho_A (d_A^2 amplitudes) is library-owned. */
 typedef struct {
     double W[3];        /* W_alpha, alpha = 2, 3, 4 (NaN above pw_set_moments)     */
@@ -308,7 +309,8 @@ PW_API pw_status pw_set_moments(pw_ctx ctx, int max_alpha);
  * events bracket the kernel's execution on the context stream): class 0 =
  * single-workgroup family kernel (small n), 1 = first transform pass (products and
  * the low 12 index bits, 15 for single precision n = 23..28), 2 = middle column
- * pass, 3 = final column pass with the reductions.  pw_timing_read synchronises the
+ * pass, 3 = final column pass with the reductions, 4 = the reduced density matrix of
+ * pw_mixed (families: 1 per launch).  pw_timing_read synchronises the
  * recorded events and returns, for one class, the number of timed launches,
  * their summed duration in milliseconds and the families they processed.
  * pw_timing_reset clears the accumulators. */

@@ -48,6 +48,7 @@ bool fault(const char* what) {
     } while (0)
 
 constexpr int MAX_QUBITS = 32;
+constexpr int PW_KCLASSES = 5;   // timed kernel classes (see pw_timing_enable)
 constexpr int EXACT_MAX_QUBITS = 26;
 constexpr int FAMILY_VALUES_MAX_QUBITS = 26;
 constexpr int SWEEP_SLOTS = 16384;   // partial sums of an exact sweep (4096 families each)
@@ -149,16 +150,16 @@ struct pw_ctx_s {
     int max_alpha = 4;
     // launch timing (measurement)
     int timing_every = 0;
-    uint64_t launches[4] = {0, 0, 0, 0};
+    uint64_t launches[PW_KCLASSES] = {};
     struct Pair {
         hipEvent_t a, b;
         int kclass, families;
     };
     std::vector<Pair> pending;
     std::vector<hipEvent_t> pool;
-    double total_ms[4] = {0, 0, 0, 0};
-    uint64_t samples[4] = {0, 0, 0, 0};
-    uint64_t sampled_families[4] = {0, 0, 0, 0};
+    double total_ms[PW_KCLASSES] = {};
+    uint64_t samples[PW_KCLASSES] = {};
+    uint64_t sampled_families[PW_KCLASSES] = {};
     LaunchTimer timer{};
     // learned proposal (library-owned device buffers)
     struct Made {
@@ -1234,7 +1235,7 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
         c->rho_bytes = bytes;
     }
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
-    PW_HIP(reduced_density(dbl, c->psi, c->n, n_a, c->rho, c->stream));
+    PW_HIP(reduced_density(dbl, c->psi, c->n, n_a, c->rho, c->stream, timer_of(c)));
     FamilyRes* fam = at<FamilyRes>(c, c->L.fam);
     for (size_t x0 = 0; x0 < dA; x0 += MAX_BATCH) {
         const int nb = (int)((dA - x0) < (size_t)MAX_BATCH ? (dA - x0) : (size_t)MAX_BATCH);
@@ -1445,14 +1446,15 @@ pw_status pw_timing_enable(pw_ctx c, int every) {
     if (s != PW_OK) return s;
     if (every < 0) return fail(PW_ERR_ARG, "every must be >= 0");
     c->timing_every = every;
-    for (int k = 0; k < 4; ++k) c->launches[k] = 0;
+    for (int k = 0; k < PW_KCLASSES; ++k) c->launches[k] = 0;
     return PW_OK;
 }
 
 pw_status pw_timing_read(pw_ctx c, int kclass, uint64_t* samples, double* total_ms, uint64_t* families) {
     pw_status s = check_ctx(c);
     if (s != PW_OK) return s;
-    if (kclass < 0 || kclass > 3) return fail(PW_ERR_ARG, "kernel class %d outside [0, 3]", kclass);
+    if (kclass < 0 || kclass >= PW_KCLASSES)
+        return fail(PW_ERR_ARG, "kernel class %d outside [0, %d]", kclass, PW_KCLASSES - 1);
     for (auto& p : c->pending) {
         PW_HIP(hipEventSynchronize(p.b));
         float ms = 0.f;
@@ -1477,7 +1479,7 @@ pw_status pw_timing_reset(pw_ctx c) {
     double b;
     s = pw_timing_read(c, 0, &a, &b, &a);
     if (s != PW_OK) return s;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < PW_KCLASSES; ++k) {
         c->total_ms[k] = 0;
         c->samples[k] = 0;
         c->sampled_families[k] = 0;

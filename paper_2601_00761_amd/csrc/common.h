@@ -62,7 +62,7 @@ Plan make_plan(int n, bool dbl);
 // that the launch attaches to the kernel's own dispatch (hipExtLaunchKernel start
 // and stop events, i.e. the kernel's execution interval on its stream), and
 // commit() files them.  Kernel classes: 0 fused, 1 first pass, 2 middle column
-// pass, 3 final column pass.
+// pass, 3 final column pass, 4 reduced density matrix (mixed states).
 struct LaunchTimer {
     bool (*take)(void* self, int kclass, hipEvent_t* start, hipEvent_t* stop);
     void (*commit)(void* self, int kclass, int families, hipEvent_t start, hipEvent_t stop);
@@ -83,9 +83,11 @@ hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, c
 hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* parts, int64_t nfam, FamilyRes* out,
                              hipStream_t st);
 
-// Mixed states: rho_A = Psi Psi^dagger of the first na qubits (d_A x d_A, row-major),
-// and the families x_A = x0 .. x0 + nb - 1 of the reduced state (na - 1 <= 13 / 12).
-hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st);
+// Mixed states: rho_A = Psi Psi^dagger of the first na qubits (d_A x d_A, row-major; the
+// 64 x 64 tiles on and above the diagonal), and the families x_A = x0 .. x0 + nb - 1 of
+// the reduced state (na - 1 <= 13 / 12).
+hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st,
+                           const LaunchTimer* tm = nullptr);
 hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, uint64_t x0, int nb, double eps,
                               FamilyRes* out, hipStream_t st);
 

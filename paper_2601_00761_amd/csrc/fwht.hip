@@ -264,6 +264,16 @@ __device__ __forceinline__ void load_products_hi(const cx<R>* __restrict__ psi, 
 //     h(a) = sum_e conj(psi(a, e)) psi(a ^ x_A, e) = rho_A[a ^ x_A, a],
 // rho_A = Psi Psi^dagger the reduced density matrix (row-major, d_A x d_A).  h has the
 // same Hermitian symmetry as f_x, so the half-size transform applies unchanged.
+// Only the 64 x 64 tiles of rho_A on and above the diagonal are formed (rho_A is
+// Hermitian); an entry below them is read as the conjugate of its mirror.
+template <typename R>
+__device__ __forceinline__ cx<R> rho_at(const cx<R>* __restrict__ rho, size_t dA, uint32_t r, uint32_t c) {
+    if ((r >> 6) <= (c >> 6)) return rho[(size_t)r * dA + c];
+    cx<R> v = rho[(size_t)c * dA + r];
+    v.im = -v.im;
+    return v;
+}
+
 template <typename R, int TL, int RL>
 __device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ rho, int na, uint32_t x, R (&re)[1 << RL],
                                              R (&im)[1 << RL]) {
@@ -276,7 +286,7 @@ __device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ rho, int 
         for (int j = 0; j < (1 << RL); ++j) {
             const uint32_t bp = tid + ((uint32_t)j << TL);
             const uint32_t b = (bp & lowmask) | ((bp & ~lowmask) << 1);
-            const cx<R> v = rho[(size_t)(b ^ x) * dA + b];
+            const cx<R> v = rho_at(rho, dA, b ^ x, b);
             re[j] = v.re;
             im[j] = v.im;
         }
@@ -522,12 +532,14 @@ k_fused_reduced(const cx<R>* __restrict__ rho, int na, uint64_t x0, R eps, Famil
     if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, na);
 }
 
-// rho_A[a, a'] = sum_e psi(a + e d_A) conj(psi(a' + e d_A)): 64 x 64 output tiles, e in
-// chunks of 16 staged through LDS, 4 x 4 outputs per thread.
+// rho_A[a, a'] = sum_e psi(a + e d_A) conj(psi(a' + e d_A)): 64 x 64 output tiles on and
+// above the diagonal (blocks below it return at once), e in chunks of 16 staged through
+// LDS, 4 x 4 outputs per thread.
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
     __shared__ cx<R> ta[16][64], tb[16][64];
+    if (blockIdx.y > blockIdx.x) return;
     const uint32_t dA = 1u << na;
     const uint64_t dE = 1ull << ne;
     const uint32_t r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
@@ -1202,14 +1214,15 @@ hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* part
     return hipGetLastError();
 }
 
-hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st) {
+hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st,
+                           const LaunchTimer* tm) {
     const unsigned tiles = (unsigned)(((1u << na) + 63) / 64);
     if (dbl)
-        hipLaunchKernelGGL(k_rho<double>, dim3(tiles, tiles), dim3(256), 0, st, (const cx<double>*)psi, na, n - na,
-                           (cx<double>*)rho);
+        PW_LAUNCH(tm, 4, 1, k_rho<double>, dim3(tiles, tiles), dim3(256), st, (const cx<double>*)psi, na, n - na,
+                  (cx<double>*)rho);
     else
-        hipLaunchKernelGGL(k_rho<float>, dim3(tiles, tiles), dim3(256), 0, st, (const cx<float>*)psi, na, n - na,
-                           (cx<float>*)rho);
+        PW_LAUNCH(tm, 4, 1, k_rho<float>, dim3(tiles, tiles), dim3(256), st, (const cx<float>*)psi, na, n - na,
+                  (cx<float>*)rho);
     return hipGetLastError();
 }
 
