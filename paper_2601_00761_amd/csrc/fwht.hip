@@ -532,68 +532,130 @@ k_fused_reduced(const cx<R>* __restrict__ rho, int na, uint64_t x0, R eps, Famil
     if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, na);
 }
 
-// rho_A[a, a'] = sum_e psi(a + e d_A) conj(psi(a' + e d_A)): 64 x 64 output tiles on and
-// above the diagonal (blocks below it return at once), e in chunks of 16 staged through
-// LDS, 4 x 4 outputs per thread.
+// One 16 x 16 x 4 matrix-core step D += A B in the transform precision.  Operands: lane l
+// gives A[l mod 16][l / 16] and B[l / 16][l mod 16]; result element v of lane l is
+// D[i][l mod 16] with i = 4 (l / 16) + v (FP32) or l / 16 + 4 v (FP64).
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+    typedef mf4 acc;
+    static __device__ __forceinline__ acc step(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct Mfma<double> {
+    typedef md4 acc;
+    static __device__ __forceinline__ acc step(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+// rho_A[a, a'] = sum_e psi(a + e d_A) conj(psi(a' + e d_A)) on the matrix cores: one
+// workgroup per 64 x 64 output tile on and above the diagonal (blocks below it return
+// at once), wave w the 32 x 32 quarter (rows 32 (w / 2), columns 32 (w mod 2)) as 2 x 2
+// blocks of 16 x 16.  Per 4 values of e a block takes four real products,
+//   re += Ar Br^T + Ai Bi^T,  im += Ai Br^T - Ar Bi^T.
+// e runs in chunks of 16 through two LDS buffers: the next chunk's loads are issued into
+// registers before the current chunk's products and stored to the other buffer after
+// them, so one barrier per chunk separates both uses of a buffer.
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
-    __shared__ cx<R> ta[16][64], tb[16][64];
+    constexpr int LD = 64 + 4;   // row pitch of a staged chunk (4 elements of padding)
+    __shared__ cx<R> ta[2][16][LD], tb[2][16][LD];
     if (blockIdx.y > blockIdx.x) return;
     const uint32_t dA = 1u << na;
     const uint64_t dE = 1ull << ne;
     const uint32_t r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    R accr[4][4], acci[4][4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+    // thread t stages elements l = t + 256 k (k < 4) of each 16 x 64 chunk: e = l >> 6, a = l & 63
+    const int aa = threadIdx.x & 63, ee0 = threadIdx.x >> 6;
+    cx<R> pa[4], pb[4];
+    auto fetch = [&](uint64_t e0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = R(0);
-    for (uint64_t e0 = 0; e0 < dE; e0 += 16) {
-        for (int l = threadIdx.x; l < 16 * 64; l += 256) {
-            const int ee = l >> 6, aa = l & 63;
-            const uint64_t e = e0 + ee;
-            cx<R> va, vb;
-            va.re = va.im = vb.re = vb.im = R(0);
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t e = e0 + (uint64_t)(ee0 + 4 * k);
+            pa[k].re = pa[k].im = pb[k].re = pb[k].im = R(0);
             if (e < dE) {
-                if (r0 + aa < dA) va = psi[(size_t)(r0 + aa) + (e << na)];
-                if (c0 + aa < dA) vb = psi[(size_t)(c0 + aa) + (e << na)];
+                if (r0 + aa < dA) pa[k] = psi[(size_t)(r0 + aa) + (e << na)];
+                if (c0 + aa < dA) pb[k] = psi[(size_t)(c0 + aa) + (e << na)];
             }
-            ta[ee][aa] = va;
-            tb[ee][aa] = vb;
         }
-        __syncthreads();
-#pragma unroll 4
-        for (int ee = 0; ee < 16; ++ee) {
-            cx<R> a[4], b[4];
+    };
+    auto stage = [&](int buf) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = ta[ee][ty * 4 + i];
-                b[i] = tb[ee][tx * 4 + i];
+        for (int k = 0; k < 4; ++k) {
+            ta[buf][ee0 + 4 * k][aa] = pa[k];
+            tb[buf][ee0 + 4 * k][aa] = pb[k];
+        }
+    };
+    typename Mfma<R>::acc accr[2][2], acci[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accr[bi][bj][v] = acci[bi][bj][v] = R(0);
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    const int kl = lane >> 4, il = lane & 15;
+    for (uint64_t e0 = 0; e0 < dE; e0 += 16) {
+        const bool more = e0 + 16 < dE;
+        if (more) fetch(e0 + 16);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int e = 4 * ks + kl;
+            R ar[2], ai[2], nar[2], br[2], bim[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const cx<R> va = ta[buf][e][wr + 16 * b + il];
+                const cx<R> vb = tb[buf][e][wc + 16 * b + il];
+                ar[b] = va.re;
+                ai[b] = va.im;
+                nar[b] = -va.re;
+                br[b] = vb.re;
+                bim[b] = vb.im;
             }
+            // the four products in turn over the eight accumulators, so that consecutive
+            // steps never wait on each other's results
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    // a conj(b)
-                    accr[i][j] = fma(a[i].re, b[j].re, fma(a[i].im, b[j].im, accr[i][j]));
-                    acci[i][j] = fma(a[i].im, b[j].re, fma(-a[i].re, b[j].im, acci[i][j]));
-                }
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj) {
+                        accr[bi][bj] = Mfma<R>::step(p ? ai[bi] : ar[bi], p ? bim[bj] : br[bj], accr[bi][bj]);
+                        acci[bi][bj] = Mfma<R>::step(p ? nar[bi] : ai[bi], p ? bim[bj] : br[bj], acci[bi][bj]);
+                    }
         }
-        __syncthreads();
+        if (more) {
+            // the other buffer was last read in the previous chunk, before the barrier
+            // that closed it
+            stage(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t r = r0 + ty * 4 + i, c = c0 + tx * 4 + j;
-            if (r < dA && c < dA) {
-                cx<R> v;
-                v.re = accr[i][j];
-                v.im = acci[i][j];
-                rho[(size_t)r * dA + c] = v;
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t r = r0 + wr + 16 * bi + Mfma<R>::row(lane, v), c = c0 + wc + 16 * bj + il;
+                if (r < dA && c < dA) {
+                    cx<R> o;
+                    o.re = accr[bi][bj][v];
+                    o.im = acci[bi][bj][v];
+                    rho[(size_t)r * dA + c] = o;
+                }
             }
-        }
 }
 
 // Intermediate tiles of the 2^15-point plans belong to families of 2^21 and more
