@@ -258,6 +258,54 @@ def mixed_leg(pw, torch, stream):
             "legs": out}
 
 
+HAAR_N = 24
+
+
+def haar_leg(pw, torch, stream, draws):
+    """Second workload (Supplemental Material, brick-wall circuits): N = 24 states from
+    d_H open-chain brick-wall layers of Haar two-qubit gates on |0...0>, complex64.  For
+    each depth: the paper's Monte Carlo estimator (x uniform over x != 0, plus x = 0) with
+    `draws` draws before and after Clifford preconditioning by 2N brick-wall layers, and the
+    exact-marginal estimator after it.  Reports M_2 +- sigma, the relative spread r_2 of
+    the per-draw terms, and the wall time of each estimate."""
+    import numpy as np
+    import synth
+    n = HAAR_N
+    out = []
+    for depth in (1, 2, 4):
+        seed = synth.SEED_BASE + 6 + depth
+        kinds, qubits, mats = synth.gates_to_arrays(synth.random_brickwall_haar(n, depth, seed))
+        psi0 = np.zeros(1 << n, dtype=np.complex64)
+        psi0[0] = 1.0
+        ctx = pw.Context(0, stream)
+        pw.pw_set_moments(ctx.h, 2)
+        ctx.upload(psi0, pw.PW_C64)
+        ctx.apply_gates(kinds, qubits, mats)
+        row = {"d_H": depth}
+
+        def est(tag, sampler, s):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.mc(sampler, 1e-4, 64, draws + 1, 0.0, s)
+            torch.cuda.synchronize()
+            row[tag] = {"M2": r["M"][0], "M2_se": r["M_se"][0], "r2": r["r"][0], "families": r["n_samples"],
+                        "seconds": time.perf_counter() - t0}
+
+        est("uniform_before", pw.PW_SAMPLER_UNIFORM_NZ, seed + 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.precondition(2 * n, seed + 2)
+        torch.cuda.synchronize()
+        row["precondition_s"] = time.perf_counter() - t0
+        est("uniform_after", pw.PW_SAMPLER_UNIFORM_NZ, seed + 3)
+        est("marginal_after", pw.PW_SAMPLER_MARGINAL_NZ, seed + 4)
+        ctx.close()
+        out.append(row)
+    return {"workload": "N=%d open brick-wall Haar circuits of depth d_H on |0..0>, complex64; %d draws per estimate; "
+                        "Clifford preconditioning with %d brick-wall layers" % (n, draws, 2 * n),
+            "depths": out}
+
+
 MULTI_STATES = 64
 MULTI_X = 64
 
@@ -414,6 +462,9 @@ def main():
                     help="families per launch (0: the library default for the state size)")
     ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=None,
                     help="also run the N=30 learned-vs-plain proposal comparison (minutes; off by default)")
+    ap.add_argument("--haar-leg", action="store_true",
+                    help="add the Haar brick-wall leg (N=24, d_H = 1, 2, 4; r_2 before / after preconditioning)")
+    ap.add_argument("--haar-draws", type=int, default=2048, help="draws per estimate in the Haar brick-wall leg")
     ap.add_argument("--mixed-leg", action="store_true",
                     help="add the mixed-state leg (N=24, n_a = 14 / 13, complex64 / complex128)")
     ap.add_argument("--multistate-leg", action="store_true",
@@ -555,6 +606,8 @@ def main():
         out["multi_state"] = multistate_leg(pw, torch, stream)
     if args.mixed_leg:
         out["mixed_state"] = mixed_leg(pw, torch, stream)
+    if args.haar_leg:
+        out["haar_brickwall"] = haar_leg(pw, torch, stream, args.haar_draws)
     if args.learned_leg is not None:
         kinds = args.learned_leg or ["psi_m", "tdoped"]
         out["learned_vs_plain"] = [learned_leg(pw, torch, stream, k, args.learned_draws, args.learned_pilot)
