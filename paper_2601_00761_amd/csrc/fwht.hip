@@ -74,6 +74,61 @@ template <> struct Math<double> {
     static constexpr double tiny = 1e-300;
 };
 
+// FP64 log2 for the reductions by a 256-entry table: v = 2^e m, m in [1, 2), c = 1 + i/256
+// with i the top 8 fraction bits of m (so m - c is exact and 0 <= r = (m - c)/c < 2^-8),
+// log2 v = e + log2 c + log2(1 + r), the last by its series through r^6 (truncation below
+// r^7 / (7 ln 2) < 2^-58).  For m >= 1.5 the entry holds log2(c / 2) and e counts one more,
+// so that v just below a power of two does not lose its small logarithm to cancellation.
+// A few ulp (checked against 120-bit logarithms over 1e-300 .. 3; absolute error below
+// 4e-18 within 1 % of 1).  Each workgroup fills its table once (1/c by IEEE division,
+// log2 by the series above); a lookup then costs about ten FP64 operations against some
+// twenty-five for the series alone.
+struct Lg2Entry {
+    double inv, lg;   // 1 / c_i, log2 c_i (log2(c_i / 2) for i >= 128)
+};
+constexpr int LG2_TAB = 256;
+
+// All threads of the workgroup call this (it ends with a barrier).
+__device__ __forceinline__ void lg2_table_init(Lg2Entry* tab) {
+    for (int i = threadIdx.x; i < LG2_TAB; i += blockDim.x) {
+        const double c = 1.0 + (double)i / LG2_TAB;
+        tab[i].inv = 1.0 / c;
+        tab[i].lg = Math<double>::lg2(i >= LG2_TAB / 2 ? 0.5 * c : c);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double lg2_tab(double v, const Lg2Entry* tab) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    const uint32_t hi = (uint32_t)(bits >> 32);
+    const uint32_t i = (hi >> 12) & (LG2_TAB - 1u);
+    const int e = (int)(hi >> 20) - 1023 + (int)(i >> 7);   // v is a positive normal number
+    const double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    const double c = __longlong_as_double((long long)(0x3FF0000000000000ull | ((uint64_t)i << 44)));
+    const Lg2Entry t = tab[i];
+    const double r = (m - c) * t.inv;
+    constexpr double L = 1.4426950408889634;   // 1 / ln 2
+    double p = -L / 6.0;
+    p = fma(p, r, L / 5.0);
+    p = fma(p, r, -L / 4.0);
+    p = fma(p, r, L / 3.0);
+    p = fma(p, r, -L / 2.0);
+    p = fma(p, r, L);
+    return ((double)e + t.lg) + r * p;
+}
+
+// log2 in the reductions: the hardware FP32 instruction, or the FP64 table.
+template <typename R>
+__device__ __forceinline__ R red_lg2(R v, const Lg2Entry* tab) {
+    if constexpr (sizeof(R) == 4) return Math<float>::lg2(v);
+    else return lg2_tab(v, tab);
+}
+
+// The table a kernel needs for its reductions: one per workgroup for FP64, none for FP32.
+template <typename R> struct Lg2Shared {
+    static constexpr int n = sizeof(R) == 8 ? LG2_TAB : 1;
+};
+
 // Window layout: register bits [A, A + RL) of the tile index, thread bits the rest.
 template <int A, int RL>
 __device__ __forceinline__ uint32_t thread_part(uint32_t tid) {
@@ -315,7 +370,8 @@ struct AccD {
 // |F|^2 below (1-eps)^2) only need a second look when the maximum exceeds
 // (1-eps)^2, which is rare outside stabilizer-like families.
 template <typename R, int RL, int MOM>
-__device__ __forceinline__ AccD reduce_points(const R (&re)[1 << RL], const R (&im)[1 << RL], bool x0, R eps) {
+__device__ __forceinline__ AccD reduce_points(const R (&re)[1 << RL], const R (&im)[1 << RL], bool x0, R eps,
+                                              const Lg2Entry* tab) {
     // transform-precision partial sums over at most 16 points (32 magnitudes), then FP64
     constexpr int CH = (1 << RL) < 16 ? (1 << RL) : 16;
     double D1, D2, D3, D4, DE;
@@ -329,7 +385,7 @@ __device__ __forceinline__ AccD reduce_points(const R (&re)[1 << RL], const R (&
             s2 += t2;
             if constexpr (MOM >= 3) s3 = fma(t2, t, s3);
             if constexpr (MOM >= 4) s4 = fma(t2, t2, s4);
-            ent = fma(t, Math<R>::lg2(fmax(t, Math<R>::tiny)), ent);
+            ent = fma(t, red_lg2<R>(fmax(t, Math<R>::tiny), tab), ent);
             mx = fmax(mx, t);
         };
         if (x0) {
@@ -506,12 +562,14 @@ k_fused(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     constexpr int NT = 1 << TL;
     __shared__ cx<R> lds[Lds<K>::elems];
     __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
+    __shared__ Lg2Entry lg2t[Lg2Shared<R>::n];
     const uint32_t slot = blockIdx.x;
     const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);  // device lists: x mod 2^n
     R re[1 << RL], im[1 << RL];
     load_products<R, TL, RL>(psi, n - 1, (uint32_t)x, 0u, re, im);
+    if constexpr (sizeof(R) == 8) lg2_table_init(lg2t);
     tile_fwht<R, TL, RL, 0>(re, im, lds);
-    const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
+    const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, lg2t), shw);
     if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, n);
 }
 
@@ -523,12 +581,14 @@ k_fused_reduced(const cx<R>* __restrict__ rho, int na, uint64_t x0, R eps, Famil
     constexpr int NT = 1 << TL;
     __shared__ cx<R> lds[Lds<K>::elems];
     __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
+    __shared__ Lg2Entry lg2t[Lg2Shared<R>::n];
     const uint32_t slot = blockIdx.x;
     const uint64_t x = x0 + slot;
     R re[1 << RL], im[1 << RL];
     load_reduced<R, TL, RL>(rho, na, (uint32_t)x, re, im);
+    if constexpr (sizeof(R) == 8) lg2_table_init(lg2t);
     tile_fwht<R, TL, RL, 0>(re, im, lds);
-    const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
+    const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, lg2t), shw);
     if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, na);
 }
 
@@ -856,6 +916,9 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
         const uint32_t J = (uint32_t)j << TL;
         ld_point<SPLIT>(pin + (J & WM) + ((size_t)(J >> W) << lo), re[j], im[j]);
     }
+    // the FP64 log2 table of the reductions, filled while the loads are in flight
+    __shared__ Lg2Entry lg2t[LAST ? Lg2Shared<R>::n : 1];
+    if constexpr (LAST && sizeof(R) == 8) lg2_table_init(lg2t);
     tile_fwht<R, TL, RL, W, SPLIT>(re, im, lds);
     if constexpr (!LAST) {
         constexpr int A = final_window<TL, RL, W>();
@@ -869,7 +932,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
     } else {
         __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
         const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);
-        const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps), shw);
+        const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, lg2t), shw);
         if (threadIdx.x == 0) parts[(size_t)slot * G + bid] = raw_res(tot, x);
     }
 }
