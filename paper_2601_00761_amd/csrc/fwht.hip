@@ -196,7 +196,7 @@ __host__ __device__ constexpr uint32_t pads(uint32_t i) { return i + (i >> RL); 
 
 template <typename R, int TL, int RL, int AO, int AN, bool TRAIL = true>
 __device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL], R* buf) {
-    static_assert(RL >= 5, "the split buffer is sized for one pad element in 32 or fewer");
+    static_assert(RL >= 4, "the split buffer pads one element in 2^min(RL, 5)");
     const uint32_t tid = threadIdx.x;
     R* wo = buf + pads<RL>(thread_part<AO, RL>(tid));
     const R* rn = buf + pads<RL>(thread_part<AN, RL>(tid));
@@ -214,10 +214,10 @@ __device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL
     if constexpr (TRAIL) __syncthreads();
 }
 
-// LDS bytes of a tile of 2^K points.
-template <typename R, int K, bool SPLIT>
+// LDS bytes of a tile of 2^K points (split buffers pad one element per 2^min(RL, 5)).
+template <typename R, int K, bool SPLIT, int RL>
 struct LdsBytes {
-    static constexpr size_t v = SPLIT ? ((size_t)(1 << K) + ((1 << K) >> 5)) * sizeof(R)
+    static constexpr size_t v = SPLIT ? ((size_t)(1 << K) + ((1 << K) >> (RL < 5 ? RL : 5))) * sizeof(R)
                                       : ((size_t)(1 << K) + ((1 << K) >> 4)) * sizeof(cx<R>);
 };
 
@@ -774,7 +774,7 @@ __global__ void __launch_bounds__(1 << TL)
 k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0,
         cx<R>* __restrict__ work) {
     constexpr int K = TL + RL;
-    __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT>::v];
+    __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT, RL>::v];
     const int nh = n - 1;
     const uint32_t tile = blockIdx.x, slot = blockIdx.y;
     const uint32_t x = (uint32_t)((xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull));
@@ -885,14 +885,16 @@ k_first_shared(const cx<R>* __restrict__ psi, int n, uint64_t x0, int fam, cx<R>
 // A tile is 2^S rows (stride 2^lo) by 2^W consecutive columns, W = K - S.
 // Grid: (2^(nh - K), families).  LAST: reduce to one partial per workgroup
 // (parts[family][block]) instead of writing the spectrum back.
-template <typename R, int TL, int RL, int S, bool LAST, int MOM, bool SPLIT = false>
+// SPLIT: the exchange moves real then imaginary parts through one buffer of half the
+// size; STREAM: nontemporal loads and stores (tiles far beyond what the caches hold).
+template <typename R, int TL, int RL, int S, bool LAST, int MOM, bool SPLIT = false, bool STREAM = SPLIT>
 __global__ void __launch_bounds__(1 << TL)
 k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
          FamilyRes* __restrict__ parts) {
     constexpr int K = TL + RL;
     constexpr int NT = 1 << TL;
     constexpr int W = K - S;
-    __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT>::v];
+    __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT, RL>::v];
     const int nh = n - 1;
     const int cbits = lo - W;
     // Workgroups are dealt round-robin to the 8 XCDs; when a family has a multiple of
@@ -914,7 +916,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) {
         const uint32_t J = (uint32_t)j << TL;
-        ld_point<SPLIT>(pin + (J & WM) + ((size_t)(J >> W) << lo), re[j], im[j]);
+        ld_point<STREAM>(pin + (J & WM) + ((size_t)(J >> W) << lo), re[j], im[j]);
     }
     // the FP64 log2 table of the reductions, filled while the loads are in flight
     __shared__ Lg2Entry lg2t[LAST ? Lg2Shared<R>::n : 1];
@@ -927,7 +929,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
             const uint32_t J = (uint32_t)j << A;
-            st_point<SPLIT>(pout + (J & WM) + ((size_t)(J >> W) << lo), re[j], im[j]);
+            st_point<STREAM>(pout + (J & WM) + ((size_t)(J >> W) << lo), re[j], im[j]);
         }
     } else {
         __shared__ AccD shw[NT / 64 > 0 ? NT / 64 : 1];
@@ -1129,11 +1131,14 @@ template <typename R, int TL, bool LAST, int MOM>
 hipError_t launch_column_t(int s, dim3 grid, cx<R>* work, int n, int lo, const uint64_t* xs, uint64_t x0, R eps,
                            FamilyRes* parts, hipStream_t st, const LaunchTimer* tm) {
     const int kc = LAST ? 3 : 2;
+    // the FP64 reducing pass exchanges real and imaginary parts in turn: half the LDS,
+    // so that four workgroups per CU overlap their loads with the FP64 reductions
+    constexpr bool SPLIT = LAST && sizeof(R) == 8;
     switch (s) {
 #define PW_COL(S)                                                                                                    \
     case S:                                                                                                          \
-        PW_LAUNCH(tm, kc, (int)grid.y, (k_column<R, TL, COL_RL, S, LAST, MOM>), grid, dim3(1 << TL), st, work, n, lo, \
-                  xs, x0, eps, parts);                                                                               \
+        PW_LAUNCH(tm, kc, (int)grid.y, (k_column<R, TL, COL_RL, S, LAST, MOM, SPLIT, false>), grid, dim3(1 << TL), st, \
+                  work, n, lo, xs, x0, eps, parts);                                                                  \
         return hipGetLastError();
         PW_COL(1) PW_COL(2) PW_COL(3) PW_COL(4) PW_COL(5) PW_COL(6) PW_COL(7) PW_COL(8) PW_COL(9)
 #undef PW_COL
