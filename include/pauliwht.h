@@ -259,8 +259,9 @@ PW_API pw_status pw_mc_learned(pw_ctx ctx, double eps, int batch, uint64_t max_s
  *   M_alpha(rho_A) = log2(W_alpha)/(1 - alpha) - n_a - S_2(rho_A),
  *   W_alpha = sum_{P on A} |Tr(rho_A P)|^{2 alpha} / d_A^alpha,  S_2 = -log2 Tr rho_A^2.
  * rho_A = Psi Psi^dagger (Psi[a, e] = psi(a + 2^{n_a} e)) is formed on the device
- * (its 64 x 64 tiles on and above the diagonal: it is Hermitian), then every x_A
- * family is the n_a-bit WHT of h(a) = rho_A[a ^ x_A, a].  1 <= n_a <=
+ * (the tiles on and above the diagonal, on the matrix cores; it is Hermitian) and
+ * stored family by family, then every x_A family is the n_a-bit WHT of
+ * h(a) = rho_A[a ^ x_A, a].  1 <= n_a <=
  * min(n, 14 (c64) / 13 (c128)); rho_A (d_A^2 amplitudes) is library-owned. */
 typedef struct {
     double W[3];        /* W_alpha, alpha = 2, 3, 4 (NaN above pw_set_moments)     */

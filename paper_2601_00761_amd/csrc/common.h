@@ -83,8 +83,8 @@ hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, c
 hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* parts, int64_t nfam, FamilyRes* out,
                              hipStream_t st);
 
-// Mixed states: rho_A = Psi Psi^dagger of the first na qubits (d_A x d_A, row-major; the
-// 64 x 64 tiles on and above the diagonal), and the families x_A = x0 .. x0 + nb - 1 of
+// Mixed states: rho_A = Psi Psi^dagger of the first na qubits, stored family-major as
+// D[x_A][a] = rho_A[a ^ x_A, a] (d_A x d_A), and the families x_A = x0 .. x0 + nb - 1 of
 // the reduced state (na - 1 <= 13 / 12).
 hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st,
                            const LaunchTimer* tm = nullptr);

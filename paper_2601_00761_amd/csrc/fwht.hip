@@ -317,23 +317,16 @@ __device__ __forceinline__ void load_products_hi(const cx<R>* __restrict__ psi, 
 // Mixed states (Supplemental Material, mixed states): for Paulis supported on the
 // first n_a qubits the family of x_A is the n_a-bit WHT of
 //     h(a) = sum_e conj(psi(a, e)) psi(a ^ x_A, e) = rho_A[a ^ x_A, a],
-// rho_A = Psi Psi^dagger the reduced density matrix (row-major, d_A x d_A).  h has the
-// same Hermitian symmetry as f_x, so the half-size transform applies unchanged.
-// Only the 64 x 64 tiles of rho_A on and above the diagonal are formed (rho_A is
-// Hermitian); an entry below them is read as the conjugate of its mirror.
-template <typename R>
-__device__ __forceinline__ cx<R> rho_at(const cx<R>* __restrict__ rho, size_t dA, uint32_t r, uint32_t c) {
-    if ((r >> 6) <= (c >> 6)) return rho[(size_t)r * dA + c];
-    cx<R> v = rho[(size_t)c * dA + r];
-    v.im = -v.im;
-    return v;
-}
-
+// rho_A = Psi Psi^dagger the reduced density matrix.  It is stored family by family,
+// D[x_A][a] = rho_A[a ^ x_A, a] (d_A x d_A, row x_A is the h of family x_A), so that a
+// family reads one contiguous row.  h has the same Hermitian symmetry as f_x, so the
+// half-size transform applies unchanged.
 template <typename R, int TL, int RL>
-__device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ rho, int na, uint32_t x, R (&re)[1 << RL],
+__device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ D, int na, uint32_t x, R (&re)[1 << RL],
                                              R (&im)[1 << RL]) {
     const uint32_t tid = threadIdx.x;
     const size_t dA = (size_t)1 << na;
+    const cx<R>* row = D + (size_t)x * dA;
     if (x != 0u) {
         const int p = 31 - __builtin_clz(x);
         const uint32_t lowmask = (1u << p) - 1u;
@@ -341,17 +334,18 @@ __device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ rho, int 
         for (int j = 0; j < (1 << RL); ++j) {
             const uint32_t bp = tid + ((uint32_t)j << TL);
             const uint32_t b = (bp & lowmask) | ((bp & ~lowmask) << 1);
-            const cx<R> v = rho_at(rho, dA, b ^ x, b);
+            const cx<R> v = row[b];
             re[j] = v.re;
             im[j] = v.im;
         }
     } else {
+        // h_0(a) = rho_A[a, a] is real: the two halves of a packed as re / im
         const uint32_t half = (uint32_t)(dA >> 1);
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
             const uint32_t bp = tid + ((uint32_t)j << TL);
-            re[j] = rho[(size_t)bp * dA + bp].re;
-            im[j] = rho[(size_t)(bp + half) * dA + bp + half].re;
+            re[j] = row[bp].re;
+            im[j] = row[bp + half].re;
         }
     }
 }
@@ -592,7 +586,7 @@ k_fused_reduced(const cx<R>* __restrict__ rho, int na, uint64_t x0, R eps, Famil
     if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, na);
 }
 
-// One 16 x 16 x 4 matrix-core step D += A B in the transform precision.  Operands: lane l
+// One 16 x 16 x 4 matrix-core step (accumulator += A B) in the transform precision.  Operands: lane l
 // gives A[l mod 16][l / 16] and B[l / 16][l mod 16]; result element v of lane l is
 // D[i][l mod 16] with i = 4 (l / 16) + v (FP32) or l / 16 + 4 v (FP64).
 typedef float mf4 __attribute__((ext_vector_type(4)));
@@ -613,19 +607,25 @@ template <> struct Mfma<double> {
     static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
-// rho_A[a, a'] = sum_e psi(a + e d_A) conj(psi(a' + e d_A)) on the matrix cores: one
-// workgroup per 64 x 64 output tile on and above the diagonal (blocks below it return
-// at once), wave w the 32 x 32 quarter (rows 32 (w / 2), columns 32 (w mod 2)) as 2 x 2
-// blocks of 16 x 16.  Per 4 values of e a block takes four real products,
+// rho_A[a, a'] = sum_e psi(a + e d_A) conj(psi(a' + e d_A)) on the matrix cores, written to
+// the family-major D (above): one workgroup per 64 x 64 tile of rho_A on and above the
+// diagonal (blocks below it return at once; rho_A is Hermitian), wave w the 32 x 32
+// quarter (rows 32 (w / 2), columns 32 (w mod 2)) as 2 x 2 blocks of 16 x 16.  Per 4
+// values of e a block takes four real products,
 //   re += Ar Br^T + Ai Bi^T,  im += Ai Br^T - Ar Bi^T.
 // e runs in chunks of 16 through two LDS buffers: the next chunk's loads are issued into
 // registers before the current chunk's products and stored to the other buffer after
 // them, so one barrier per chunk separates both uses of a buffer.
 template <typename R>
 __global__ void __launch_bounds__(256)
-k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
+k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ D) {
     constexpr int LD = 64 + 4;   // row pitch of a staged chunk (4 elements of padding)
-    __shared__ cx<R> ta[2][16][LD], tb[2][16][LD];
+    constexpr int CH = 16 * LD;  // one staged chunk of 16 values of e
+    constexpr int OP = 64 + 1;   // row pitch of the output block staged at the end
+    static_assert(64 * OP <= 4 * CH, "the output block reuses the chunk buffers");
+    __shared__ cx<R> sh[4 * CH];
+    auto ta = [&](int buf, int e, int a) -> cx<R>& { return sh[buf * CH + e * LD + a]; };
+    auto tb = [&](int buf, int e, int a) -> cx<R>& { return sh[(2 + buf) * CH + e * LD + a]; };
     if (blockIdx.y > blockIdx.x) return;
     const uint32_t dA = 1u << na;
     const uint64_t dE = 1ull << ne;
@@ -649,8 +649,8 @@ k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
     auto stage = [&](int buf) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            ta[buf][ee0 + 4 * k][aa] = pa[k];
-            tb[buf][ee0 + 4 * k][aa] = pb[k];
+            ta(buf, ee0 + 4 * k, aa) = pa[k];
+            tb(buf, ee0 + 4 * k, aa) = pb[k];
         }
     };
     typename Mfma<R>::acc accr[2][2], acci[2][2];
@@ -674,8 +674,8 @@ k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
             R ar[2], ai[2], nar[2], br[2], bim[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                const cx<R> va = ta[buf][e][wr + 16 * b + il];
-                const cx<R> vb = tb[buf][e][wc + 16 * b + il];
+                const cx<R> va = ta(buf, e, wr + 16 * b + il);
+                const cx<R> vb = tb(buf, e, wc + 16 * b + il);
                 ar[b] = va.re;
                 ai[b] = va.im;
                 nar[b] = -va.re;
@@ -702,20 +702,41 @@ k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ rho) {
             buf ^= 1;
         }
     }
+    // The tile T = rho_A[r0 + ri, c0 + ci] goes to D through LDS: entry (ri, ci) belongs to
+    // family x = r ^ c at a = c, and its mirror conj T (rho_A is Hermitian) to the same
+    // family at a = r.  With R = r0 / 64, C = c0 / 64 the first fills the 64 x 64 block
+    // (R ^ C, C) of D at (ri ^ ci, ci), the second (off the diagonal) the block (R ^ C, R) at
+    // (ri ^ ci, ri); every block of D is written by exactly one workgroup, row by row.
+    __syncthreads();   // every wave is done with the chunk buffers
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const uint32_t r = r0 + wr + 16 * bi + Mfma<R>::row(lane, v), c = c0 + wc + 16 * bj + il;
-                if (r < dA && c < dA) {
-                    cx<R> o;
-                    o.re = accr[bi][bj][v];
-                    o.im = acci[bi][bj][v];
-                    rho[(size_t)r * dA + c] = o;
-                }
+                cx<R> o;
+                o.re = accr[bi][bj][v];
+                o.im = acci[bi][bj][v];
+                sh[(wr + 16 * bi + Mfma<R>::row(lane, v)) * OP + wc + 16 * bj + il] = o;
             }
+    __syncthreads();
+    const uint32_t xb = (blockIdx.y ^ blockIdx.x) * 64;
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+        const uint32_t xl = (uint32_t)idx >> 6, cl = (uint32_t)idx & 63u;
+        const uint32_t x = xb + xl, a = c0 + cl;
+        if (x < dA && a < dA) D[(size_t)x * dA + a] = sh[(xl ^ cl) * OP + cl];
+    }
+    if (blockIdx.y != blockIdx.x) {
+        for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+            const uint32_t xl = (uint32_t)idx >> 6, rl = (uint32_t)idx & 63u;
+            const uint32_t x = xb + xl, a = r0 + rl;
+            if (x < dA && a < dA) {
+                cx<R> v = sh[rl * OP + (xl ^ rl)];
+                v.im = -v.im;
+                D[(size_t)x * dA + a] = v;
+            }
+        }
+    }
 }
 
 // Intermediate tiles of the 2^15-point plans belong to families of 2^21 and more
