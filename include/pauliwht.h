@@ -261,8 +261,10 @@ PW_API pw_status pw_mc_learned(pw_ctx ctx, double eps, int batch, uint64_t max_s
  * rho_A = Psi Psi^dagger (Psi[a, e] = psi(a + 2^{n_a} e)) is formed on the device
  * (the tiles on and above the diagonal, on the matrix cores; it is Hermitian) and
  * stored family by family, then every x_A family is the n_a-bit WHT of
- * h(a) = rho_A[a ^ x_A, a].  1 <= n_a <=
- * min(n, 14 (c64) / 13 (c128)); rho_A (d_A^2 amplitudes) is library-owned. */
+ * h(a) = rho_A[a ^ x_A, a] (one workgroup per family up to n_a = 14 (c64) / 13
+ * (c128), the multi-pass transform above).  1 <= n_a <= min(n, 16); rho_A (d_A^2
+ * amplitudes: 32 GiB for c64, 64 GiB for c128 at n_a = 16) and the pass buffers
+ * are library-owned. */
 typedef struct {
     double W[3];        /* W_alpha, alpha = 2, 3, 4 (NaN above pw_set_moments)     */
     double purity;      /* Tr rho_A^2 = sum_{P on A} |c_P|^2 / d_A                 */

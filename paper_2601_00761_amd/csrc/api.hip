@@ -51,6 +51,7 @@ constexpr int MAX_QUBITS = 32;
 constexpr int PW_KCLASSES = 5;   // timed kernel classes (see pw_timing_enable)
 constexpr int EXACT_MAX_QUBITS = 26;
 constexpr int FAMILY_VALUES_MAX_QUBITS = 26;
+constexpr int MIXED_MAX_QUBITS = 16;   // n_a: rho_A takes 4^16 amplitudes (32 / 64 GiB)
 constexpr int SWEEP_SLOTS = 16384;   // partial sums of an exact sweep (4096 families each)
 constexpr int64_t EXACT_CHUNK = 1 << 20;  // families per chunk of an exact sweep
 constexpr int MAX_BATCH = 4096;
@@ -1218,11 +1219,23 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
     if (s != PW_OK) return s;
     if (!out) return fail(PW_ERR_ARG, "null output");
     const bool dbl = c->dtype == PW_C128;
-    const int amax = dbl ? 13 : 14;
-    if (n_a < 1 || n_a > c->n || n_a > amax) return fail(PW_ERR_RANGE, "n_a=%d outside [1, min(n, %d)]", n_a, amax);
+    if (n_a < 1 || n_a > c->n || n_a > MIXED_MAX_QUBITS)
+        return fail(PW_ERR_RANGE, "n_a=%d outside [1, min(n, %d)]", n_a, MIXED_MAX_QUBITS);
     if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
     const size_t dA = (size_t)1 << n_a;
-    const size_t bytes = dA * dA * esize(c->dtype);
+    // library-owned: the family-major rho_A, then (families larger than one workgroup
+    // holds) the multi-pass work and partials for nbm families per launch
+    const Plan P = make_plan(n_a, dbl);
+    const size_t half_bytes = (dA >> 1) * esize(c->dtype);
+    size_t nbm = MAX_BATCH, work_b = 0, parts_b = 0;
+    if (!P.fused) {
+        nbm = ((size_t)256 << 20) / half_bytes;
+        nbm = nbm < 1 ? 1 : (nbm > 256 ? 256 : nbm);
+        work_b = align256(nbm * half_bytes);
+        parts_b = align256(nbm * (size_t)P.blocks_last * sizeof(FamilyRes));
+    }
+    const size_t rho_b = align256(dA * dA * esize(c->dtype));
+    const size_t bytes = rho_b + work_b + parts_b;
     if (c->rho_bytes < bytes) {
         if (c->rho) {
             PW_HIP(hipStreamSynchronize(c->stream));
@@ -1237,9 +1250,11 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
     PW_HIP(reduced_density(dbl, c->psi, c->n, n_a, c->rho, c->stream, timer_of(c)));
     FamilyRes* fam = at<FamilyRes>(c, c->L.fam);
-    for (size_t x0 = 0; x0 < dA; x0 += MAX_BATCH) {
-        const int nb = (int)((dA - x0) < (size_t)MAX_BATCH ? (dA - x0) : (size_t)MAX_BATCH);
-        PW_HIP(eval_reduced_batch(dbl, c->max_alpha, c->rho, n_a, x0, nb, eps, fam + x0, c->stream));
+    void* work = (char*)c->rho + rho_b;
+    FamilyRes* parts = reinterpret_cast<FamilyRes*>((char*)c->rho + rho_b + work_b);
+    for (size_t x0 = 0; x0 < dA; x0 += nbm) {
+        const int nb = (int)((dA - x0) < nbm ? (dA - x0) : nbm);
+        PW_HIP(eval_reduced_batch(dbl, c->max_alpha, c->rho, n_a, x0, nb, eps, work, parts, fam + x0, c->stream));
     }
     SweepSums* sw = at<SweepSums>(c, c->L.sweep);
     PW_HIP(reduce_families(fam, (int64_t)dA, sw, c->stream));

@@ -85,11 +85,12 @@ hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* part
 
 // Mixed states: rho_A = Psi Psi^dagger of the first na qubits, stored family-major as
 // D[x_A][a] = rho_A[a ^ x_A, a] (d_A x d_A), and the families x_A = x0 .. x0 + nb - 1 of
-// the reduced state (na - 1 <= 13 / 12).
+// the reduced state.  When make_plan(na) is not single-workgroup the families go through
+// the multi-pass transform: work holds nb * 2^(na-1) points, parts nb * blocks_last.
 hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, hipStream_t st,
                            const LaunchTimer* tm = nullptr);
 hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, uint64_t x0, int nb, double eps,
-                              FamilyRes* out, hipStream_t st);
+                              void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st);
 
 // Fixed-order sum of count per-family results.
 // Partial sums of count per-family results, FAM_PER_SLOT families per slot, written to

@@ -321,9 +321,11 @@ __device__ __forceinline__ void load_products_hi(const cx<R>* __restrict__ psi, 
 // D[x_A][a] = rho_A[a ^ x_A, a] (d_A x d_A, row x_A is the h of family x_A), so that a
 // family reads one contiguous row.  h has the same Hermitian symmetry as f_x, so the
 // half-size transform applies unchanged.
+// h values of tile `tile` (half indices (tile << K) + t + j 2^TL) of family x.
 template <typename R, int TL, int RL>
-__device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ D, int na, uint32_t x, R (&re)[1 << RL],
-                                             R (&im)[1 << RL]) {
+__device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ D, int na, uint32_t x, uint32_t tile,
+                                             R (&re)[1 << RL], R (&im)[1 << RL]) {
+    constexpr int K = TL + RL;
     const uint32_t tid = threadIdx.x;
     const size_t dA = (size_t)1 << na;
     const cx<R>* row = D + (size_t)x * dA;
@@ -332,7 +334,7 @@ __device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ D, int na
         const uint32_t lowmask = (1u << p) - 1u;
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
-            const uint32_t bp = tid + ((uint32_t)j << TL);
+            const uint32_t bp = (tile << K) + tid + ((uint32_t)j << TL);
             const uint32_t b = (bp & lowmask) | ((bp & ~lowmask) << 1);
             const cx<R> v = row[b];
             re[j] = v.re;
@@ -343,7 +345,7 @@ __device__ __forceinline__ void load_reduced(const cx<R>* __restrict__ D, int na
         const uint32_t half = (uint32_t)(dA >> 1);
 #pragma unroll
         for (int j = 0; j < (1 << RL); ++j) {
-            const uint32_t bp = tid + ((uint32_t)j << TL);
+            const uint32_t bp = (tile << K) + tid + ((uint32_t)j << TL);
             re[j] = row[bp].re;
             im[j] = row[bp + half].re;
         }
@@ -579,7 +581,7 @@ k_fused_reduced(const cx<R>* __restrict__ rho, int na, uint64_t x0, R eps, Famil
     const uint32_t slot = blockIdx.x;
     const uint64_t x = x0 + slot;
     R re[1 << RL], im[1 << RL];
-    load_reduced<R, TL, RL>(rho, na, (uint32_t)x, re, im);
+    load_reduced<R, TL, RL>(rho, na, (uint32_t)x, 0u, re, im);
     if constexpr (sizeof(R) == 8) lg2_table_init(lg2t);
     tile_fwht<R, TL, RL, 0>(re, im, lds);
     const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, lg2t), shw);
@@ -789,8 +791,10 @@ k_fused_store(const cx<R>* __restrict__ psi, int n, uint64_t x, cx<R>* __restric
 }
 
 // First pass of a multi-pass transform: products + low K index bits of one tile.
+// HSRC: the values come from the family-major reduced density matrix of the mixed-state
+// path (psi is D and n is n_a) instead of products of the state.
 // Grid: (tiles per family, families).
-template <typename R, int TL, int RL, bool SPLIT = false>
+template <typename R, int TL, int RL, bool SPLIT = false, bool HSRC = false>
 __global__ void __launch_bounds__(1 << TL)
 k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0,
         cx<R>* __restrict__ work) {
@@ -800,7 +804,8 @@ k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     const uint32_t tile = blockIdx.x, slot = blockIdx.y;
     const uint32_t x = (uint32_t)((xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull));
     R re[1 << RL], im[1 << RL];
-    if (x >= (1u << K)) load_products_hi<R, TL, RL>(psi, x, tile, re, im);
+    if constexpr (HSRC) load_reduced<R, TL, RL>(psi, n, x, tile, re, im);
+    else if (x >= (1u << K)) load_products_hi<R, TL, RL>(psi, x, tile, re, im);
     else load_products<R, TL, RL>(psi, nh, x, tile, re, im);
     tile_fwht<R, TL, RL, 0, SPLIT>(re, im, lds);
     store_tile<R, TL, RL, SPLIT>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
@@ -1377,9 +1382,41 @@ hipError_t reduced_density(bool dbl, const void* psi, int n, int na, void* rho, 
     return hipGetLastError();
 }
 
+// Families of the reduced state too large for one workgroup: the first pass reads h rows
+// of D, then the column passes and the per-family finalisation of the state path.
+template <typename R, int MOM>
+hipError_t eval_reduced_mp_t(const Plan& P, const void* D, uint64_t x0, int nb, double eps, void* work,
+                             FamilyRes* parts, FamilyRes* out, hipStream_t st) {
+    if (P.fused || P.k1 != K_FIRST) return hipErrorInvalidValue;
+    const R e = (R)eps;
+    const uint32_t tiles = 1u << (P.nh - P.k1);
+    hipLaunchKernelGGL((k_first<R, 8, 4, false, true>), dim3(tiles, nb), dim3(256), 0, st, (const cx<R>*)D, P.n,
+                       nullptr, x0, (cx<R>*)work);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (int i = 0; i < P.npass; ++i) {
+        const bool last = i + 1 == P.npass;
+        err = last ? launch_column<R, true, MOM>(P.ktile, P.s[i], P.nh, nb, (cx<R>*)work, P.n, P.lo[i], nullptr, x0,
+                                                 e, parts, st, nullptr)
+                   : launch_column<R, false, 2>(P.ktile, P.s[i], P.nh, nb, (cx<R>*)work, P.n, P.lo[i], nullptr, x0, e,
+                                                parts, st, nullptr);
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
+    return hipGetLastError();
+}
+
 hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, uint64_t x0, int nb, double eps,
-                              FamilyRes* out, hipStream_t st) {
+                              void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st) {
     if (nb <= 0) return hipSuccess;
+    const Plan P = make_plan(na, dbl);
+    if (!P.fused) {
+        if (dbl)
+            return max_alpha >= 4 ? eval_reduced_mp_t<double, 4>(P, rho, x0, nb, eps, work, parts, out, st)
+                                  : eval_reduced_mp_t<double, 2>(P, rho, x0, nb, eps, work, parts, out, st);
+        return max_alpha >= 4 ? eval_reduced_mp_t<float, 4>(P, rho, x0, nb, eps, work, parts, out, st)
+                              : eval_reduced_mp_t<float, 2>(P, rho, x0, nb, eps, work, parts, out, st);
+    }
     if (dbl)
         return max_alpha >= 4 ? launch_reduced<double, 4>(rho, na, x0, nb, eps, out, st)
                               : launch_reduced<double, 2>(rho, na, x0, nb, eps, out, st);

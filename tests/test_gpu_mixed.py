@@ -14,7 +14,9 @@ pw = pytest.importorskip("paper_2601_00761_amd")
 
 
 @pytest.mark.parametrize("n,n_a,dtype", [(10, 1, 0), (10, 3, 0), (10, 6, 1), (10, 10, 0), (16, 8, 0), (16, 8, 1),
-                                         (18, 12, 0), (17, 13, 1)])
+                                         (18, 12, 0), (17, 13, 1),
+                                         # families beyond one workgroup: the multi-pass transform
+                                         (15, 14, 0), (16, 15, 1)])
 def test_mixed_matches_oracle(n, n_a, dtype):
     psi = as_input(synth.haar_state(n, 700 + n + n_a), dtype)
     log("mixed n=%d n_a=%d dtype=%d" % (n, n_a, dtype))
@@ -56,3 +58,22 @@ def test_mixed_product_closed_form():
     ctx.close()
     assert abs(g["S2"]) < 1e-10
     assert abs(g["M"][0] - n_xy * math.log2(4 / 3)) < 1e-9
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_mixed_product_closed_form_largest_subsystem(dtype):
+    # n_a = 16 (the library's limit; multi-pass families): A = T on 16 stabilizer states,
+    # B a 2-qubit Haar state, so rho_A is pure with M_2 = n_xy log2(4/3), S_2 = 0
+    labels = synth.stabilizer_product_spec(16, 91)
+    phiA = synth.states.stabilizer_product(labels, t_on=set(range(16)))
+    phiB = synth.haar_state(2, 92)
+    psi = np.kron(phiB, phiA)
+    n_xy = sum(l[0] != "z" for l in labels)
+    log("mixed product n_a=16 dtype=%d" % dtype)
+    ctx = make_ctx(as_input(psi, dtype), dtype)
+    g = pw.pw_mixed(ctx.h, 16, 1e-7 if dtype == 0 else 1e-4)
+    ctx.close()
+    tol = 1e-9 if dtype == 0 else 2e-4
+    assert abs(g["S2"]) < tol
+    assert abs(g["M"][0] - n_xy * math.log2(4 / 3)) < tol * 16
+    assert g["families"] == 1 << 16
