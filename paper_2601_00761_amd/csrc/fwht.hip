@@ -613,8 +613,9 @@ template <> struct Mfma<double> {
 // the family-major D (above): one workgroup per 64 x 64 tile of rho_A on and above the
 // diagonal (blocks below it return at once; rho_A is Hermitian), wave w the 32 x 32
 // quarter (rows 32 (w / 2), columns 32 (w mod 2)) as 2 x 2 blocks of 16 x 16.  Per 4
-// values of e a block takes four real products,
-//   re += Ar Br^T + Ai Bi^T,  im += Ai Br^T - Ar Bi^T.
+// values of e a block takes the four real products of
+//   re += Ar Br^T + Ai Bi^T,  im += Ai Br^T - Ar Bi^T
+// (FP64), or three (FP32, below).
 // e runs in chunks of 16 through two LDS buffers: the next chunk's loads are issued into
 // registers before the current chunk's products and stored to the other buffer after
 // them, so one barrier per chunk separates both uses of a buffer.
@@ -655,13 +656,21 @@ k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ D) {
             tb(buf, ee0 + 4 * k, aa) = pb[k];
         }
     };
-    typename Mfma<R>::acc accr[2][2], acci[2][2];
+    // FP32: three real products per block (Gauss): t1 = Ar Br^T, t2 = Ai Bi^T,
+    // t3 = (Ar + Ai)(Br - Bi)^T; then re = t1 + t2, im = t3 - t1 + t2.  FP64 keeps the
+    // four products (t1 = re, t2 = im): a third accumulator set would leave one wave per
+    // SIMD.
+    constexpr bool GAUSS = sizeof(R) == 4;
+    typename Mfma<R>::acc t1[2][2], t2[2][2], t3[GAUSS ? 2 : 1][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) accr[bi][bj][v] = acci[bi][bj][v] = R(0);
+            for (int v = 0; v < 4; ++v) {
+                t1[bi][bj][v] = t2[bi][bj][v] = R(0);
+                if constexpr (GAUSS) t3[bi][bj][v] = R(0);
+            }
     fetch(0);
     stage(0);
     __syncthreads();
@@ -673,28 +682,43 @@ k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ D) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int e = 4 * ks + kl;
-            R ar[2], ai[2], nar[2], br[2], bim[2];
+            R ar[2], ai[2], br[2], bim[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const cx<R> va = ta(buf, e, wr + 16 * b + il);
                 const cx<R> vb = tb(buf, e, wc + 16 * b + il);
                 ar[b] = va.re;
                 ai[b] = va.im;
-                nar[b] = -va.re;
                 br[b] = vb.re;
                 bim[b] = vb.im;
             }
-            // the four products in turn over the eight accumulators, so that consecutive
-            // steps never wait on each other's results
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
+            // the products in turn over the accumulators, so that consecutive steps never
+            // wait on each other's results
+            if constexpr (GAUSS) {
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                    for (int bj = 0; bj < 2; ++bj) {
-                        accr[bi][bj] = Mfma<R>::step(p ? ai[bi] : ar[bi], p ? bim[bj] : br[bj], accr[bi][bj]);
-                        acci[bi][bj] = Mfma<R>::step(p ? nar[bi] : ai[bi], p ? bim[bj] : br[bj], acci[bi][bj]);
-                    }
+                    for (int bj = 0; bj < 2; ++bj) t1[bi][bj] = Mfma<R>::step(ar[bi], br[bj], t1[bi][bj]);
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj) t2[bi][bj] = Mfma<R>::step(ai[bi], bim[bj], t2[bi][bj]);
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+                        t3[bi][bj] = Mfma<R>::step(ar[bi] + ai[bi], br[bj] - bim[bj], t3[bi][bj]);
+            } else {
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 2; ++bj) {
+                            t1[bi][bj] = Mfma<R>::step(p ? ai[bi] : ar[bi], p ? bim[bj] : br[bj], t1[bi][bj]);
+                            t2[bi][bj] = Mfma<R>::step(p ? -ar[bi] : ai[bi], p ? bim[bj] : br[bj], t2[bi][bj]);
+                        }
+            }
         }
         if (more) {
             // the other buffer was last read in the previous chunk, before the barrier
@@ -717,8 +741,13 @@ k_rho(const cx<R>* __restrict__ psi, int na, int ne, cx<R>* __restrict__ D) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 cx<R> o;
-                o.re = accr[bi][bj][v];
-                o.im = acci[bi][bj][v];
+                if constexpr (GAUSS) {
+                    o.re = t1[bi][bj][v] + t2[bi][bj][v];
+                    o.im = (t3[bi][bj][v] - t1[bi][bj][v]) + t2[bi][bj][v];
+                } else {
+                    o.re = t1[bi][bj][v];
+                    o.im = t2[bi][bj][v];
+                }
                 sh[(wr + 16 * bi + Mfma<R>::row(lane, v)) * OP + wc + 16 * bj + il] = o;
             }
     __syncthreads();
