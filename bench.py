@@ -93,6 +93,24 @@ def fill_ceiling(torch, nbytes=256 << 20, reps=20):
     return gbps
 
 
+def copy_ceiling(torch, nbytes=1 << 30, reps=10):
+    """GB/s (read + write bytes) of a plain device-to-device copy of nbytes (torch copy_,
+    events on torch's stream): what HBM sustains for a stream that reads and writes."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbps
+
+
 def prepare_state(pw, torch, n, seed):
     import numpy as np
     import synth
@@ -184,6 +202,7 @@ def mc_leg(pw, torch, stream, eta, timing_every):
     t_first = load_traffic("k_first", "pmc_traffic_c64_n28_mc.json")
     t_col = load_traffic("k_column", "pmc_traffic_c64_n28_mc.json")
     traffic = t_first + t_col if t_first is not None and t_col is not None else None
+    copy = copy_ceiling(torch)
     return {"workload": "N=%d T-doped Clifford state, eta=%d, N_T=%d, complex64; Clifford preconditioning %d "
                         "brick-wall layers; x ~ exact marginal (x != 0) plus x = 0, %d per batch; stop at "
                         "std-err(M_2) <= %g or %d families" % (n, eta, 2 * n, 2 * n, MC_BATCH, MC_TARGET_SE, MC_MAX),
@@ -201,6 +220,11 @@ def mc_leg(pw, torch, stream, eta, timing_every):
                          "unit": "GB/s", "frac": round(alg / (per_fam_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                          "traffic": traffic,
                          "traffic_GBps": round(traffic / (per_fam_us * 1e-6) / 1e9, 1) if traffic else None,
+                         "copy_ceiling": {"GBps": round(copy, 1),
+                                          "traffic_frac": round(traffic / (per_fam_us * 1e-6) / 1e9 / copy, 4)
+                                          if traffic else None,
+                                          "note": "device-to-device copy of 1 GiB (torch copy_), read + write bytes "
+                                                  "over time, same GPU"},
                          "note": "one read of psi per family over the summed kernel time of the path; traffic = "
                                  "rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per family of the first and reducing passes"}}
 
