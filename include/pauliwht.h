@@ -29,8 +29,10 @@
  *
  * Ownership.  Device buffers (the state, the workspace) belong to the caller and
  * are borrowed; the library never frees them.  Host arrays passed in or out are
- * caller-allocated.  The library allocates device memory of its own only when no
- * workspace was set (then it owns and frees it at pw_ctx_destroy).
+ * caller-allocated.  The library allocates device memory of its own for the
+ * workspace when none was set, for pw_mixed's reduced density matrix and pass
+ * buffers, and for the learned proposal (pw_made_init); it owns these, reuses
+ * them while large enough, and frees them at pw_ctx_destroy.
  *
  * Streams.  All device work of a context is enqueued on the stream given at
  * creation (NULL = the default stream).  Calls that return host results
@@ -119,8 +121,8 @@ PW_API pw_status pw_ctx_create(pw_ctx* out, int device, void* hip_stream);
 PW_API pw_status pw_ctx_destroy(pw_ctx ctx);
 
 /* Device bytes of workspace needed to evaluate up to `x_batch` families of an
- * n-qubit state of the given dtype per launch, including the CDF used by the
- * marginal sampler.  1 <= n <= 32. */
+ * n-qubit state of the given dtype per launch, including the two FP64 prefix
+ * tables of the marginal sampler (2 * 2^n doubles).  1 <= n <= 32. */
 PW_API pw_status pw_workspace_size(int n_qubits, pw_dtype dtype, int x_batch, size_t* bytes);
 
 /* Lend a device buffer (256-byte aligned) as workspace; the library carves all
