@@ -582,7 +582,10 @@ def main():
                 "path_us_per_family": round(path_us, 4),
                 "hbm_equivalent": {"algorithmic_bytes_per_family": alg_bytes_family,
                                    "GBps": round(alg_bytes_family / (path_us * 1e-6) / 1e9, 1),
-                                   "note": "one read of psi per family over the whole path time"}}
+                                   "frac_of_hbm_peak": round(alg_bytes_family / (path_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                                             4),
+                                   "note": "one read of psi per family over the whole path time (the state is served "
+                                           "from L2/MALL at N = 20, so this is an equivalent, not HBM traffic)"}}
     if traffic is not None:
         roofline["traffic_GBps"] = round(traffic / (d["avg_ms"] * 1e-3) / 1e9, 1)
         roofline["traffic_note"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch (L2 <-> fabric: MALL or HBM) "
