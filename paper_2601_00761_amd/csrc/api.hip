@@ -178,6 +178,10 @@ struct pw_ctx_s {
     } made;
     void* rho = nullptr;        // reduced density matrix (library-owned)
     size_t rho_bytes = 0;
+    void* pin = nullptr;        // pinned host staging of pw_eval_states (library-owned)
+    size_t pin_bytes = 0;
+    void* nrm = nullptr;        // per-state norm slots of pw_eval_states (library-owned)
+    size_t nrm_bytes = 0;
     // graph replay of Monte Carlo sampling steps
     bool use_graphs = false;
     hipStream_t gstream = nullptr;  // non-blocking capture stream (default priority)
@@ -445,6 +449,8 @@ pw_status pw_ctx_destroy(pw_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->made.block) (void)hipFree(c->made.block);
     if (c->rho) (void)hipFree(c->rho);
+    if (c->pin) (void)hipHostFree(c->pin);
+    if (c->nrm) (void)hipFree(c->nrm);
     if (c->gstream) {
         (void)hipStreamSynchronize(c->gstream);
         (void)hipStreamDestroy(c->gstream);
@@ -1386,45 +1392,113 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
     const int saved_n = c->n;
     const pw_dtype saved_dt = c->dtype;
     const size_t cap = c->ws_bytes;
-    std::vector<FamilyRes> res((size_t)n_x);
-    std::vector<uint64_t> sx;
-    std::vector<int64_t> pos;
-    for (int k = 0; k < nstates && s == PW_OK; ++k) {
-        sx.clear();
-        pos.clear();
-        for (int64_t i = 0; i < n_x; ++i)
-            if (state_idx[i] == k) {
-                sx.push_back(xs[i]);
-                pos.push_back(i);
-            }
-        if (sx.empty()) continue;
+    // the list grouped by state (a stable counting sort; positions kept for the scatter)
+    std::vector<int64_t> start((size_t)nstates + 1, 0), order((size_t)n_x);
+    for (int64_t i = 0; i < n_x; ++i) ++start[(size_t)state_idx[i] + 1];
+    for (int k = 0; k < nstates; ++k) start[(size_t)k + 1] += start[(size_t)k];
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n_x; ++i) order[(size_t)fill[(size_t)state_idx[i]]++] = i;
+    }
+    // pinned host staging (norms, grouped x, results) and the states' norm slots on the
+    // device: the whole call synchronises twice, once for the norm checks of all states
+    // and once for all results
+    const size_t o_x = align256((size_t)nstates * 2 * sizeof(double));
+    const size_t o_r = o_x + align256((size_t)n_x * sizeof(uint64_t));
+    const size_t pin_need = o_r + align256((size_t)n_x * sizeof(FamilyRes));
+    if (c->pin_bytes < pin_need) {
+        if (c->pin) {
+            PW_HIP(hipStreamSynchronize(c->stream));
+            PW_HIP(hipHostFree(c->pin));
+            c->pin = nullptr;
+            c->pin_bytes = 0;
+        }
+        if (fault("alloc")) return fail(PW_ERR_HIP, "hipHostMalloc: injected failure (PW_FAULT=alloc)");
+        PW_HIP(hipHostMalloc(&c->pin, pin_need, hipHostMallocDefault));
+        c->pin_bytes = pin_need;
+    }
+    const size_t nrm_need = (size_t)nstates * 2 * sizeof(double);
+    if (c->nrm_bytes < nrm_need) {
+        if (c->nrm) {
+            PW_HIP(hipStreamSynchronize(c->stream));
+            PW_HIP(hipFree(c->nrm));
+            c->nrm = nullptr;
+            c->nrm_bytes = 0;
+        }
+        if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+        PW_HIP(hipMalloc(&c->nrm, nrm_need));
+        c->nrm_bytes = nrm_need;
+    }
+    double* hnorm = reinterpret_cast<double*>(c->pin);
+    uint64_t* hx = reinterpret_cast<uint64_t*>((char*)c->pin + o_x);
+    FamilyRes* hres = reinterpret_cast<FamilyRes*>((char*)c->pin + o_r);
+    for (int64_t j = 0; j < n_x; ++j) hx[j] = xs[order[(size_t)j]];
+    double* dnrm = reinterpret_cast<double*>(c->nrm);
+    // bind state k's plan and layout to the context
+    auto use_state = [&](int k) -> pw_status {
         c->psi = states[k].psi;
         c->n = states[k].n;
         c->dtype = states[k].dtype;
         c->P = make_plan(c->n, c->dtype == PW_C128);
         const int B = Bk[(size_t)k];
         c->L = layout_for(c->n, c->dtype, B);
-        if (c->L.total > cap) {
-            s = fail(PW_ERR_WORKSPACE, "state %d does not fit the shared workspace", k);
-            break;
-        }
+        if (c->L.total > cap) return fail(PW_ERR_WORKSPACE, "state %d does not fit the shared workspace", k);
         c->batch = B;
         const int tuned = tuned_batch(c->device, c->n, c->dtype);
         c->run_batch = tuned > 0 && tuned < B ? tuned : B;
         c->cdf_valid = false;
-        double nrm = 0.0;
-        s = run_norm(c, &nrm);
+        return PW_OK;
+    };
+    // 1. the norm of every state that has families (stream order keeps the shared
+    //    partial-sum region of one state from being overwritten before it is reduced)
+    for (int k = 0; k < nstates && s == PW_OK; ++k) {
+        if (start[(size_t)k + 1] == start[(size_t)k]) continue;
+        s = use_state(k);
         if (s != PW_OK) break;
-        const double tol = c->dtype == PW_C128 ? 1e-10 : 1e-5;
-        if (!(fabs(nrm - 1.0) <= tol)) {
-            s = fail(PW_ERR_NOT_NORMALIZED, "state %d: <psi|psi> = %.17g", k, nrm);
-            break;
-        }
-        std::vector<FamilyRes> r(sx.size());
-        s = eval_host(c, sx.data(), (int64_t)sx.size(), eps, r.data());
-        if (s != PW_OK) break;
-        for (size_t j = 0; j < sx.size(); ++j) res[pos[j]] = r[j];
+        unsigned* bad = reinterpret_cast<unsigned*>(dnrm + 2 * k + 1);
+        if (hipMemsetAsync(bad, 0, sizeof(unsigned), c->stream) != hipSuccess ||
+            norm2(c->dtype == PW_C128, c->psi, c->n, at<double>(c, c->L.norm), norm2_parts(c->n), dnrm + 2 * k, bad,
+                  c->stream) != hipSuccess)
+            s = fail(PW_ERR_HIP, "state %d: norm launch failed", k);
     }
+    if (s == PW_OK) {
+        if (hipMemcpyAsync(hnorm, dnrm, nrm_need, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            s = fail(PW_ERR_HIP, "norm copy failed");
+    }
+    for (int k = 0; k < nstates && s == PW_OK; ++k) {
+        if (start[(size_t)k + 1] == start[(size_t)k]) continue;
+        unsigned hb;
+        memcpy(&hb, hnorm + 2 * k + 1, sizeof hb);
+        const double nrm = hnorm[2 * k];
+        const double tol = states[k].dtype == PW_C128 ? 1e-10 : 1e-5;
+        if (hb) s = fail(PW_ERR_NOT_NORMALIZED, "state %d holds NaN or Inf amplitudes", k);
+        else if (!(fabs(nrm - 1.0) <= tol)) s = fail(PW_ERR_NOT_NORMALIZED, "state %d: <psi|psi> = %.17g", k, nrm);
+    }
+    // 2. every state's families: x in, results out through the pinned staging, no
+    //    synchronisation until the end (each copy and launch is ordered on the stream)
+    for (int k = 0; k < nstates && s == PW_OK; ++k) {
+        const int64_t j0 = start[(size_t)k], j1 = start[(size_t)k + 1];
+        if (j1 == j0) continue;
+        s = use_state(k);
+        if (s != PW_OK) break;
+        uint64_t* dx = at<uint64_t>(c, c->L.xs);
+        FamilyRes* dr = at<FamilyRes>(c, c->L.xres);
+        for (int64_t j = j0; j < j1 && s == PW_OK; j += c->L.xcap) {
+            const int64_t nb = (j1 - j) < c->L.xcap ? (j1 - j) : c->L.xcap;
+            if (hipMemcpyAsync(dx, hx + j, (size_t)nb * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess) {
+                s = fail(PW_ERR_HIP, "x list copy failed");
+                break;
+            }
+            s = eval_device(c, dx, 0, nb, eps, dr);
+            if (s != PW_OK) break;
+            if (hipMemcpyAsync(hres + j, dr, (size_t)nb * sizeof(FamilyRes), hipMemcpyDeviceToHost, c->stream) !=
+                hipSuccess)
+                s = fail(PW_ERR_HIP, "result copy failed");
+        }
+    }
+    if (s == PW_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = fail(PW_ERR_HIP, "synchronisation failed");
     // restore the bound state (the workspace stays carved for the largest)
     c->psi = saved_psi;
     c->n = saved_n;
@@ -1437,7 +1511,7 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         if (s == PW_OK) s = s2;
     }
     if (s != PW_OK) return s;
-    memcpy(out, res.data(), (size_t)n_x * sizeof(FamilyRes));
+    for (int64_t j = 0; j < n_x; ++j) memcpy(out + order[(size_t)j], hres + j, sizeof(FamilyRes));
     return PW_OK;
 }
 

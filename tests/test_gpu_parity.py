@@ -426,6 +426,39 @@ def test_eval_states_uneven_sizes_match_single_state_calls():
     ctx.close()
 
 
+def test_eval_states_rejects_a_bad_state_and_keeps_the_bound_one():
+    # all norms are checked before any family is evaluated: a state off by 1 % is
+    # rejected, the context's own bound state is restored, and a second call with the
+    # good states (and a repeated call, which reuses the staging) succeeds
+    import torch
+    n0 = 12
+    psi0 = synth.haar_state(n0, 1300)
+    ctx = make_ctx(psi0, pw.PW_C128)
+    before = ctx.eval_x(np.array([0, 3, 77], dtype=np.uint64), 1e-7)
+    good = [torch.tensor(synth.haar_state(n, 1310 + n), device="cuda:0") for n in (10, 14)]
+    bad = torch.tensor(synth.haar_state(11, 1320) * 1.01, device="cuda:0")
+    states = [(good[0], 10, 0), (bad, 11, 0), (good[1], 14, 0)]
+    idx = np.array([0, 1, 2, 0, 2], dtype=np.int32)
+    xs = np.array([1, 2, 3, 4, 5], dtype=np.uint64)
+    log("eval_states with a non-normalised state")
+    with pytest.raises(pw.PWError) as e:
+        pw.pw_eval_states(ctx.h, states, idx, xs, 1e-7)
+    assert e.value.status == 3
+    after = ctx.eval_x(np.array([0, 3, 77], dtype=np.uint64), 1e-7)
+    assert np.array_equal(before.view(np.uint8), after.view(np.uint8))
+    ok_states = [states[0], states[2]]
+    ok_idx = np.array([0, 1, 0, 1], dtype=np.int32)
+    ok_xs = np.array([1, 3, 4, 5], dtype=np.uint64)
+    g1 = pw.pw_eval_states(ctx.h, ok_states, ok_idx, ok_xs, 1e-7)
+    g2 = pw.pw_eval_states(ctx.h, ok_states, ok_idx, ok_xs, 1e-7)
+    ctx.close()
+    assert np.array_equal(g1.view(np.uint8), g2.view(np.uint8))
+    for k, (t, n, dt) in enumerate(ok_states):
+        sel = np.nonzero(ok_idx == k)[0]
+        r = oracle.eval_x(t.cpu().numpy(), ok_xs[sel], eps=1e-7)
+        assert np.allclose(g1["m"][sel, 0], r["m"][:, 0], rtol=1e-10, atol=0)
+
+
 def test_autotune_picks_a_candidate_and_keeps_results():
     n = 18
     psi = synth.haar_state(n, 1300).astype(np.complex64)
