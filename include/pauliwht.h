@@ -287,7 +287,10 @@ PW_API pw_status pw_autotune(pw_ctx ctx, int* best_batch, int* candidates, doubl
 /* Several states of different sizes in one call: family xs[i] of state
  * states[state_idx[i]], results to out[i] (host arrays).  One workspace serves all
  * states, sized for the largest layout; each state runs at its own families per
- * launch; every state is norm-checked.  The bound state of the context is kept. */
+ * launch.  Every state with families is norm-checked before any family is
+ * evaluated (PW_ERR_NOT_NORMALIZED names the first bad one; out is then untouched).
+ * The call synchronises the stream twice, staging x lists and results through
+ * library-owned pinned host memory.  The bound state of the context is kept. */
 typedef struct {
     void* psi;         /* device amplitudes, 256-byte aligned, borrowed */
     int n;
