@@ -43,7 +43,30 @@ def build(verbose=False):
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
+    build_example(verbose)
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(HERE, "examples", "exact_c.c")
+EXAMPLE_BIN = os.path.join(HERE, "examples", "exact_c")
+EXAMPLE_LIB = os.path.join(HERE, "examples", "libexact_c.so")
+
+
+def build_example(verbose=False):
+    """The plain-C client of the ABI (gcc, the header and the HIP runtime only), as a
+    program and as a shared object without main (loaded in-process by the tests)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    common = ["gcc", "-O2", "-std=c11", "-Wall", "-I" + os.path.join(ROOT, "include"),
+              "-I" + os.path.join(rocm, "include"), EXAMPLE_SRC]
+    link = ["-L" + HERE, "-lpauliwht", "-L" + os.path.join(rocm, "lib"), "-lamdhip64",
+            "-Wl,-rpath,$ORIGIN/..:" + os.path.join(rocm, "lib")]
+    for cmd in (common + ["-o", EXAMPLE_BIN] + link,
+                common + ["-DEXACT_C_NO_MAIN", "-fPIC", "-shared", "-o", EXAMPLE_LIB] + link):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("example build failed:\n" + r.stderr)
+    if verbose:
+        print("built", EXAMPLE_BIN, EXAMPLE_LIB)
 
 
 if __name__ == "__main__":
