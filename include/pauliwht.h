@@ -290,7 +290,10 @@ PW_API pw_status pw_autotune(pw_ctx ctx, int* best_batch, int* candidates, doubl
  * launch.  Every state with families is norm-checked before any family is
  * evaluated (PW_ERR_NOT_NORMALIZED names the first bad one; out is then untouched).
  * The call synchronises the stream twice, staging x lists and results through
- * library-owned pinned host memory.  The bound state of the context is kept. */
+ * library-owned pinned host memory.  The bound state of the context is kept, also
+ * when the call fails, except when its workspace, freed to grow for a larger state,
+ * cannot be allocated again: then no state is bound (PW_ERR_NO_STATE until the next
+ * bind or upload). */
 typedef struct {
     void* psi;         /* device amplitudes, 256-byte aligned, borrowed */
     int n;

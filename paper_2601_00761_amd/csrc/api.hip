@@ -376,7 +376,10 @@ struct Running {
 struct McGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipStream_t st = nullptr;  // the replay stream; drained first, so that a call that
+                               // fails between replays leaves no step running
     ~McGraph() {
+        if (exec && st) (void)hipStreamSynchronize(st);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
     }
@@ -412,6 +415,7 @@ pw_status mc_graph_build(pw_ctx c, pw_sampler sampler, uint64_t seed, int nb, do
     if (s != PW_OK) return s;
     if (e != hipSuccess) return fail(PW_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     PW_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    g.st = c->gstream;
     return PW_OK;
 }
 
@@ -1371,27 +1375,27 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         Bk[(size_t)k] = b;
         need = std::max(need, layout_for(states[k].n, states[k].dtype, b).total);
     }
-    if (c->ws && !c->ws_owned) {
-        if (need > c->ws_bytes) return fail(PW_ERR_WORKSPACE, "workspace too small for the largest state");
-    } else if (!c->ws || c->ws_bytes < need) {
-        if (c->ws) {
-            PW_HIP(hipStreamSynchronize(c->stream));
-            PW_HIP(hipFree(c->ws));
-            c->ws = nullptr;
-            c->ws_bytes = 0;
-        }
-        if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
-        void* p = nullptr;
-        PW_HIP(hipMalloc(&p, need));
-        c->ws = (char*)p;
-        c->ws_bytes = need;
-        c->ws_owned = true;
-    }
+    if (c->ws && !c->ws_owned && need > c->ws_bytes)
+        return fail(PW_ERR_WORKSPACE, "workspace too small for the largest state");
     const bool was_bound = c->bound;
     void* const saved_psi = c->psi;
     const int saved_n = c->n;
     const pw_dtype saved_dt = c->dtype;
-    const size_t cap = c->ws_bytes;
+    // puts the caller's bound state back (the workspace stays carved for the largest
+    // state); every exit from here on goes through it, so a failed call also keeps it
+    auto restore = [&](pw_status st) -> pw_status {
+        c->psi = saved_psi;
+        c->n = saved_n;
+        c->dtype = saved_dt;
+        c->bound = false;
+        c->cdf_valid = false;
+        if (was_bound) {
+            const pw_status s2 = prepare_workspace(c, saved_n, saved_dt);
+            if (s2 == PW_OK) c->bound = true;
+            if (st == PW_OK) st = s2;
+        }
+        return st;
+    };
     // the list grouped by state (a stable counting sort; positions kept for the scatter)
     std::vector<int64_t> start((size_t)nstates + 1, 0), order((size_t)n_x);
     for (int64_t i = 0; i < n_x; ++i) ++start[(size_t)state_idx[i] + 1];
@@ -1406,29 +1410,50 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
     const size_t o_x = align256((size_t)nstates * 2 * sizeof(double));
     const size_t o_r = o_x + align256((size_t)n_x * sizeof(uint64_t));
     const size_t pin_need = o_r + align256((size_t)n_x * sizeof(FamilyRes));
-    if (c->pin_bytes < pin_need) {
-        if (c->pin) {
-            PW_HIP(hipStreamSynchronize(c->stream));
-            PW_HIP(hipHostFree(c->pin));
-            c->pin = nullptr;
-            c->pin_bytes = 0;
-        }
-        if (fault("alloc")) return fail(PW_ERR_HIP, "hipHostMalloc: injected failure (PW_FAULT=alloc)");
-        PW_HIP(hipHostMalloc(&c->pin, pin_need, hipHostMallocDefault));
-        c->pin_bytes = pin_need;
-    }
     const size_t nrm_need = (size_t)nstates * 2 * sizeof(double);
-    if (c->nrm_bytes < nrm_need) {
-        if (c->nrm) {
-            PW_HIP(hipStreamSynchronize(c->stream));
-            PW_HIP(hipFree(c->nrm));
-            c->nrm = nullptr;
-            c->nrm_bytes = 0;
+    auto allocate = [&]() -> pw_status {
+        if (!(c->ws && !c->ws_owned) && (!c->ws || c->ws_bytes < need)) {
+            c->cdf_valid = false;  // the bound state's tables do not survive this
+            if (c->ws) {
+                PW_HIP(hipStreamSynchronize(c->stream));
+                PW_HIP(hipFree(c->ws));
+                c->ws = nullptr;
+                c->ws_bytes = 0;
+            }
+            if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+            void* p = nullptr;
+            PW_HIP(hipMalloc(&p, need));
+            c->ws = (char*)p;
+            c->ws_bytes = need;
+            c->ws_owned = true;
         }
-        if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
-        PW_HIP(hipMalloc(&c->nrm, nrm_need));
-        c->nrm_bytes = nrm_need;
-    }
+        if (c->pin_bytes < pin_need) {
+            if (c->pin) {
+                PW_HIP(hipStreamSynchronize(c->stream));
+                PW_HIP(hipHostFree(c->pin));
+                c->pin = nullptr;
+                c->pin_bytes = 0;
+            }
+            if (fault("alloc")) return fail(PW_ERR_HIP, "hipHostMalloc: injected failure (PW_FAULT=alloc)");
+            PW_HIP(hipHostMalloc(&c->pin, pin_need, hipHostMallocDefault));
+            c->pin_bytes = pin_need;
+        }
+        if (c->nrm_bytes < nrm_need) {
+            if (c->nrm) {
+                PW_HIP(hipStreamSynchronize(c->stream));
+                PW_HIP(hipFree(c->nrm));
+                c->nrm = nullptr;
+                c->nrm_bytes = 0;
+            }
+            if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+            PW_HIP(hipMalloc(&c->nrm, nrm_need));
+            c->nrm_bytes = nrm_need;
+        }
+        return PW_OK;
+    };
+    s = allocate();
+    if (s != PW_OK) return restore(s);
+    const size_t cap = c->ws_bytes;
     double* hnorm = reinterpret_cast<double*>(c->pin);
     uint64_t* hx = reinterpret_cast<uint64_t*>((char*)c->pin + o_x);
     FamilyRes* hres = reinterpret_cast<FamilyRes*>((char*)c->pin + o_r);
@@ -1499,17 +1524,7 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         }
     }
     if (s == PW_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = fail(PW_ERR_HIP, "synchronisation failed");
-    // restore the bound state (the workspace stays carved for the largest)
-    c->psi = saved_psi;
-    c->n = saved_n;
-    c->dtype = saved_dt;
-    c->bound = false;
-    c->cdf_valid = false;
-    if (was_bound) {
-        pw_status s2 = prepare_workspace(c, saved_n, saved_dt);
-        if (s2 == PW_OK) c->bound = true;
-        if (s == PW_OK) s = s2;
-    }
+    s = restore(s);
     if (s != PW_OK) return s;
     for (int64_t j = 0; j < n_x; ++j) memcpy(out + order[(size_t)j], hres + j, sizeof(FamilyRes));
     return PW_OK;
