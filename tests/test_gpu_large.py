@@ -168,3 +168,27 @@ def test_benchmark_sweep_equals_sum_of_families():
         assert abs(g["p"] - r["p"][i]) <= b["p"]
         assert abs(g["ent"] - r["ent"][i]) <= b["ent"]
         assert int(g["nu"]) == int(r["nu"][i])
+
+
+@pytest.mark.parametrize("n,dtype", [(24, 1), (26, 1), (26, 0)])
+def test_signed_family_values_largest(n, dtype):
+    # the largest states pw_family_values takes: complex64 through the 15-bit first pass
+    # and a 12-bit (n = 24) or 15-bit (n = 26) column pass written back, complex128
+    # through the 12-bit first pass and two column passes; c(x, z) = (-i)^{|x & z|} F_x(z)
+    # against the oracle's spectrum, every z
+    from gpu_util import as_input, make_ctx
+    psi = as_input(synth.haar_state(n, 500 + n), dtype)
+    ctx = make_ctx(psi, dtype)
+    z = np.arange(1 << n, dtype=np.uint64)
+    phase = np.array([1, -1j, -1, 1j])
+    tol = 1e-13 if dtype == 0 else 4 * (n + 2) * 2.0 ** -24
+    for x in (0, 1, (1 << n) - 1, 0x2A5A5A5 % (1 << n)):
+        log("family values n=%d dtype=%d x=%d" % (n, dtype, x))
+        c = ctx.family_values(x)
+        ref = phase[np.bitwise_count(z & np.uint64(x)) & 3] * oracle.spectrum(psi, x)
+        assert np.max(np.abs(ref.imag)) < 1e-12
+        err = np.max(np.abs(c - ref.real))
+        log("  max |c - c_oracle| = %.3g (bound %.3g)" % (err, tol))
+        assert err <= tol
+        del c, ref
+    ctx.close()
