@@ -130,3 +130,41 @@ def test_device_list_takes_x_mod_2n(n, dtype):
     assert np.array_equal(got["x"], xs)
     for f in ("p", "ent", "m", "gap", "nu"):
         assert np.array_equal(got[f], ref[f]), f
+
+
+def test_launch_timing_samples_every_kth_launch():
+    # pw_timing_*: every k-th launch of each kernel class is bracketed by events; for an
+    # n = 18 complex64 sweep (first pass, one reducing column pass) the two classes see
+    # the same launches, ceil(L / k) of the L launches, each with the same family count;
+    # the summed durations, scaled by k, fit inside the call's wall time
+    import time
+    n, every = 18, 4
+    ctx = make_ctx(synth.haar_state(n, 1500).astype(np.complex64), pw.PW_C64)
+    pw.pw_timing_enable(ctx.h, every)
+    pw.pw_timing_reset(ctx.h)
+    log("timing n=%d every=%d" % (n, every))
+    t0 = time.perf_counter()
+    ctx.exact(1e-4)
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    got = {k: pw.pw_timing_read(ctx.h, k) for k in range(5)}
+    assert got[0][0] == 0 and got[2][0] == 0 and got[4][0] == 0
+    (c1, ms1, f1), (c3, ms3, f3) = got[1], got[3]
+    assert c1 > 0 and (c1, f1) == (c3, f3)
+    assert f1 % c1 == 0
+    launches = (1 << n) // (f1 // c1)
+    assert c1 == -(-launches // every)
+    assert ms1 > 0 and ms3 > 0 and (ms1 + ms3) * every < 1.5 * wall_ms, (ms1, ms3, wall_ms)
+    pw.pw_timing_reset(ctx.h)
+    assert pw.pw_timing_read(ctx.h, 1) == (0, 0.0, 0)
+    pw.pw_timing_enable(ctx.h, 0)
+    ctx.exact(1e-4)
+    assert pw.pw_timing_read(ctx.h, 1)[0] == 0
+    ctx.close()
+    # a small state: the single-workgroup kernel (class 0), all 2^12 families in one launch
+    ctx = make_ctx(synth.haar_state(12, 1501), pw.PW_C128)
+    pw.pw_timing_enable(ctx.h, 1)
+    log("timing n=12 fused")
+    ctx.exact(1e-7)
+    c0, ms0, f0 = pw.pw_timing_read(ctx.h, 0)
+    ctx.close()
+    assert (c0, f0) == (1, 1 << 12) and ms0 > 0
