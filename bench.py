@@ -201,7 +201,10 @@ def mc_leg(pw, torch, stream, eta, timing_every):
     # counter-measured bytes per family of the two kernels (first pass, reducing column pass)
     t_first = load_traffic("k_first", "pmc_traffic_c64_n28_mc.json")
     t_col = load_traffic("k_column", "pmc_traffic_c64_n28_mc.json")
-    traffic = t_first + t_col if t_first is not None and t_col is not None else None
+    traffic = None
+    if t_first is not None and t_col is not None and "k_first" in kt and "k_column(last)" in kt:
+        traffic = (t_first / kt["k_first"]["families_per_launch"]
+                   + t_col / kt["k_column(last)"]["families_per_launch"])
     copy = copy_ceiling(torch)
     return {"workload": "N=%d T-doped Clifford state, eta=%d, N_T=%d, complex64; Clifford preconditioning %d "
                         "brick-wall layers; x ~ exact marginal (x != 0) plus x = 0, %d per batch; stop at "

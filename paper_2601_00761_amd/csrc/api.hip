@@ -62,7 +62,7 @@ size_t esize(pw_dtype dt) { return dt == PW_C128 ? 16 : 8; }
 
 // Workspace layout for (n, dtype, batch).
 struct Layout {
-    size_t work, parts, xs, xres, fam, sweep, cdf, cdfblk, norm, ctr, total;
+    size_t work, parts, xs, xres, xsort, perm, xres2, fam, sweep, cdf, cdfblk, norm, ctr, total;
     int64_t parts_fams;  // families whose final-pass partials the parts region holds
     int64_t xcap;        // x values / per-family results the staging regions hold
 };
@@ -99,6 +99,14 @@ Layout layout_for(int n, pw_dtype dt, int batch) {
     off += align256((size_t)L.xcap * sizeof(uint64_t));
     L.xres = off;
     off += align256((size_t)L.xcap * sizeof(FamilyRes));
+    // a list sorted by top bit for tile-sharing groups, its order and its results
+    static_assert(MAX_BATCH <= SORT_MAX, "sorted lists are staged MAX_BATCH at a time");
+    L.xsort = off;
+    off += align256((size_t)L.xcap * sizeof(uint64_t));
+    L.perm = off;
+    off += align256((size_t)L.xcap * sizeof(uint32_t));
+    L.xres2 = off;
+    off += align256((size_t)L.xcap * sizeof(FamilyRes));
     L.fam = off;
     const int64_t chunk = ((int64_t)1 << n) < EXACT_CHUNK ? ((int64_t)1 << n) : EXACT_CHUNK;
     off += align256((size_t)chunk * sizeof(FamilyRes));
@@ -126,6 +134,9 @@ int default_batch(int n, pw_dtype dt) {
     // power of two
     size_t p = 1;
     while (p * 2 <= b) p *= 2;
+    // states the caches do not hold: launches of four families, which the first pass
+    // runs in one tile-sharing group (up to 16 GiB of half spectra)
+    while (p < 4 && first_pass_group(n, dt == PW_C128, 4) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
     return (int)p;
 }
 
@@ -312,9 +323,8 @@ pw_status run_norm(pw_ctx c, double* out) {
 
 // Evaluate nx families whose x are in device memory (or x0 + i when d_xs is null),
 // results to device array d_out, in launches of the context's launch batch, on st.
-pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
-                         hipStream_t st) {
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
+                       hipStream_t st) {
     const bool dbl = c->dtype == PW_C128;
     // multi-pass plans: batches leave their partials side by side, one finalize per group
     const bool defer = !c->P.fused;
@@ -333,6 +343,26 @@ pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx
         pending += nb;
     }
     if (defer && pending > 0) PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, st));
+    return PW_OK;
+}
+
+pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
+                         hipStream_t st) {
+    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (!d_xs || c->P.fused || first_pass_group(c->n, c->dtype == PW_C128, c->run_batch) < 2)
+        return eval_list_on(c, d_xs, x0, nx, eps, d_out, st);
+    // tile-sharing groups: the list is evaluated in top-bit order, so that the families
+    // of a launch share state tiles, and the results are put back in list order
+    uint64_t* xs2 = at<uint64_t>(c, c->L.xsort);
+    uint32_t* perm = at<uint32_t>(c, c->L.perm);
+    FamilyRes* r2 = at<FamilyRes>(c, c->L.xres2);
+    for (int64_t i = 0; i < nx; i += c->L.xcap) {
+        const int m = (int)((nx - i) < c->L.xcap ? (nx - i) : c->L.xcap);
+        PW_HIP(sort_by_top_bit(d_xs + i, c->n, m, xs2, perm, st));
+        const pw_status s = eval_list_on(c, xs2, 0, m, eps, r2, st);
+        if (s != PW_OK) return s;
+        PW_HIP(scatter_results(r2, perm, m, d_out + i, st));
+    }
     return PW_OK;
 }
 

@@ -58,6 +58,19 @@ struct Plan {
 
 Plan make_plan(int n, bool dbl);
 
+// Families per group of the first pass that share their state tiles (1, 2 or 4; more
+// than 1 only for states of 512 MiB and more, and at most nb).  The workgroups of one
+// tile and group run back to back on one XCD, so the tile comes from HBM once.
+int first_pass_group(int n, bool dbl, int nb);
+
+// Grouping support for lists of families: a stable sort of nx <= SORT_MAX families by
+// the top set bit of x mod 2^n (x = 0 first), xs_sorted[j] = xs[perm[j]], so that
+// consecutive families share state tiles; and the per-family results of the sorted list
+// put back in list order, out[perm[j]] = in[j].
+constexpr int SORT_MAX = 4096;
+hipError_t sort_by_top_bit(const uint64_t* xs, int n, int nx, uint64_t* xs_sorted, uint32_t* perm, hipStream_t st);
+hipError_t scatter_results(const FamilyRes* in, const uint32_t* perm, int nx, FamilyRes* out, hipStream_t st);
+
 // Optional launch timing.  For a sampled launch, take() hands out two HIP events
 // that the launch attaches to the kernel's own dispatch (hipExtLaunchKernel start
 // and stop events, i.e. the kernel's execution interval on its stream), and

@@ -822,15 +822,30 @@ k_fused_store(const cx<R>* __restrict__ psi, int n, uint64_t x, cx<R>* __restric
 // First pass of a multi-pass transform: products + low K index bits of one tile.
 // HSRC: the values come from the family-major reduced density matrix of the mixed-state
 // path (psi is D and n is n_a) instead of products of the state.
-// Grid: (tiles per family, families).
-template <typename R, int TL, int RL, bool SPLIT = false, bool HSRC = false>
+// Grid: (tiles per family, families), or with GRP > 1 (states beyond the caches, families
+// in groups of GRP with the same top bit of x, hence the same state tile): one dimension
+// of tiles x ceil(nb / GRP) GRP workgroups, numbered so that the GRP workgroups of one
+// tile and group follow each other on one XCD (workgroups are dealt round-robin to the 8
+// XCDs): the first reads the tile from HBM, the others find it in that XCD's L2.
+// Requires tiles % 8 == 0; workgroups of the padding slots (>= nb) return at once.
+template <typename R, int TL, int RL, bool SPLIT = false, bool HSRC = false, int GRP = 1>
 __global__ void __launch_bounds__(1 << TL)
 k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0,
-        cx<R>* __restrict__ work) {
+        cx<R>* __restrict__ work, int nb) {
     constexpr int K = TL + RL;
     __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT, RL>::v];
     const int nh = n - 1;
-    const uint32_t tile = blockIdx.x, slot = blockIdx.y;
+    uint32_t tile, slot;
+    if constexpr (GRP > 1) {
+        const uint32_t t8 = 1u << (nh - K - 3);   // tiles / 8
+        const uint32_t s = blockIdx.x >> 3, r = s / GRP;
+        tile = ((r & (t8 - 1u)) << 3) | (blockIdx.x & 7u);
+        slot = (r >> (nh - K - 3)) * GRP + s % GRP;
+        if (slot >= (uint32_t)nb) return;
+    } else {
+        tile = blockIdx.x;
+        slot = blockIdx.y;
+    }
     const uint32_t x = (uint32_t)((xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull));
     R re[1 << RL], im[1 << RL];
     if constexpr (HSRC) load_reduced<R, TL, RL>(psi, n, x, tile, re, im);
@@ -992,6 +1007,49 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
         const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, lg2t), shw);
         if (threadIdx.x == 0) parts[(size_t)slot * G + bid] = raw_res(tot, x);
     }
+}
+
+// Stable counting sort of a list of at most 4096 families by the top set bit of
+// x mod 2^n (x = 0 first): xs_sorted[j] = xs[perm[j]].  One wave; lane t takes a
+// contiguous chunk of the list and keeps its key counts in its own column of h.
+__global__ void __launch_bounds__(64)
+k_sort_top(const uint64_t* __restrict__ xs, int n, int nx, uint64_t* __restrict__ xs_sorted,
+           uint32_t* __restrict__ perm) {
+    constexpr int NK = 33;   // keys 0 (x = 0) and 1..32 (top bit + 1)
+    __shared__ uint32_t h[NK][64];
+    const int t = threadIdx.x;
+    const int per = (nx + 63) / 64;
+    const int i0 = min(nx, t * per), i1 = min(nx, i0 + per);
+    const uint64_t mask = (1ull << n) - 1ull;
+    for (int k = 0; k < NK; ++k) h[k][t] = 0u;
+    for (int i = i0; i < i1; ++i) {
+        const uint64_t x = xs[i] & mask;
+        ++h[x ? 64 - __clzll((long long)x) : 0][t];
+    }
+    // exclusive prefix over (key, lane) in key-major order
+    uint32_t base = 0;
+    for (int k = 0; k < NK; ++k) {
+        const uint32_t v = h[k][t];
+        uint32_t incl = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d);
+            if (t >= d) incl += o;
+        }
+        h[k][t] = base + incl - v;
+        base += __shfl(incl, 63);
+    }
+    for (int i = i0; i < i1; ++i) {
+        const uint64_t x = xs[i] & mask;
+        const uint32_t j = h[x ? 64 - __clzll((long long)x) : 0][t]++;
+        xs_sorted[j] = xs[i];
+        perm[j] = (uint32_t)i;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_scatter_res(const FamilyRes* __restrict__ in, const uint32_t* __restrict__ perm, int nx, FamilyRes* __restrict__ out) {
+    const int j = (int)(blockIdx.x * 256u + threadIdx.x);
+    if (j < nx) out[perm[j]] = in[j];
 }
 
 // Per-family fixed-order sum of the final pass's partials.  Grid: one wave per family.
@@ -1236,6 +1294,25 @@ hipError_t launch_column(int ktile, int s, int nh, int nb, cx<R>* work, int n, i
     return launch_column_t<R, 8, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st, tm);
 }
 
+// First pass over nb families, with the tile-sharing groups where first_pass_group
+// asks for them.
+template <typename R, int TL, int RL, bool SPLIT>
+void launch_first(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, void* work,
+                  hipStream_t st, const LaunchTimer* tm) {
+    const uint32_t tiles = 1u << (P.nh - TL - RL);
+    const int grp = first_pass_group(P.n, sizeof(R) == 8, nb);
+    const uint32_t blocks = tiles * (uint32_t)((nb + grp - 1) / grp * grp);
+    if (grp == 4)
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 4>), dim3(blocks), dim3(1 << TL), st,
+                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+    else if (grp == 2)
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 2>), dim3(blocks), dim3(1 << TL), st,
+                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+    else
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT>), dim3(tiles, nb), dim3(1 << TL), st, (const cx<R>*)psi, P.n,
+                  xs, x0, (cx<R>*)work, nb);
+}
+
 template <typename R, int MOM>
 hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, double eps,
                         void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st, const LaunchTimer* tm,
@@ -1246,8 +1323,7 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
     const uint32_t tiles = 1u << (P.nh - P.k1);
     if constexpr (sizeof(R) == 4) {
         if (P.k1 == 15) {
-            PW_LAUNCH(tm, 1, nb, (k_first<float, 10, 5, true>), dim3(tiles, nb), dim3(1024), st, (const cx<float>*)psi,
-                      P.n, xs, x0, (cx<float>*)work);
+            launch_first<float, 10, 5, true>(P, psi, xs, x0, nb, work, st, tm);
             goto first_done;
         }
     }
@@ -1260,8 +1336,7 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
         PW_LAUNCH(tm, 1, nb, (k_first_shared<R, 8, 4>), dim3(tiles, nb / fam), dim3(256), st, (const cx<R>*)psi, P.n,
                   x0, fam, (cx<R>*)work);
     } else {
-        PW_LAUNCH(tm, 1, nb, (k_first<R, 8, 4>), dim3(tiles, nb), dim3(256), st, (const cx<R>*)psi, P.n, xs, x0,
-                  (cx<R>*)work);
+        launch_first<R, 8, 4, false>(P, psi, xs, x0, nb, work, st, tm);
     }
 first_done:
     hipError_t err = hipGetLastError();
@@ -1311,13 +1386,13 @@ hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* wor
     if constexpr (sizeof(R) == 4) {
         if (P.k1 == 15) {
             hipLaunchKernelGGL((k_first<float, 10, 5, true>), dim3(1u << (nh - 15), 1), dim3(1024), 0, st,
-                               (const cx<float>*)psi, P.n, (const uint64_t*)nullptr, x, (cx<float>*)work);
+                               (const cx<float>*)psi, P.n, (const uint64_t*)nullptr, x, (cx<float>*)work, 1);
             done = true;
         }
     }
     if (!done)
         hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (nh - K_FIRST), 1), dim3(256), 0, st, (const cx<R>*)psi,
-                           P.n, (const uint64_t*)nullptr, x, (cx<R>*)work);
+                           P.n, (const uint64_t*)nullptr, x, (cx<R>*)work, 1);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
@@ -1420,7 +1495,7 @@ hipError_t eval_reduced_mp_t(const Plan& P, const void* D, uint64_t x0, int nb, 
     const R e = (R)eps;
     const uint32_t tiles = 1u << (P.nh - P.k1);
     hipLaunchKernelGGL((k_first<R, 8, 4, false, true>), dim3(tiles, nb), dim3(256), 0, st, (const cx<R>*)D, P.n,
-                       nullptr, x0, (cx<R>*)work);
+                       nullptr, x0, (cx<R>*)work, nb);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
@@ -1451,6 +1526,25 @@ hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, 
                               : launch_reduced<double, 2>(rho, na, x0, nb, eps, out, st);
     return max_alpha >= 4 ? launch_reduced<float, 4>(rho, na, x0, nb, (float)eps, out, st)
                           : launch_reduced<float, 2>(rho, na, x0, nb, (float)eps, out, st);
+}
+
+int first_pass_group(int n, bool dbl, int nb) {
+    // states of 512 MiB and more: the caches do not hold the state between families
+    if (((size_t)(dbl ? 16 : 8) << n) < ((size_t)512 << 20)) return 1;
+    return nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
+}
+
+hipError_t sort_by_top_bit(const uint64_t* xs, int n, int nx, uint64_t* xs_sorted, uint32_t* perm, hipStream_t st) {
+    if (nx <= 0) return hipSuccess;
+    if (nx > SORT_MAX || n < 1 || n > 32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sort_top, dim3(1), dim3(64), 0, st, xs, n, nx, xs_sorted, perm);
+    return hipGetLastError();
+}
+
+hipError_t scatter_results(const FamilyRes* in, const uint32_t* perm, int nx, FamilyRes* out, hipStream_t st) {
+    if (nx <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_res, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, in, perm, nx, out);
+    return hipGetLastError();
 }
 
 hipError_t reduce_families(const FamilyRes* in, int64_t count, SweepSums* out, hipStream_t st) {

@@ -192,3 +192,47 @@ def test_signed_family_values_largest(n, dtype):
         assert err <= tol
         del c, ref
     ctx.close()
+
+
+@pytest.mark.parametrize("n,dtype", [(26, 1), (25, 0)])
+def test_tile_sharing_groups_keep_list_order_and_values(n, dtype):
+    # states of 512 MiB and more evaluate a list in top-bit order, four families per
+    # launch sharing their state tiles, and put the results back in list order.  A ragged
+    # unsorted list with mixed top bits gives bitwise the results of one family per launch
+    # (no groups, no sorting); sampled families agree with the oracle; graph replay of
+    # Monte Carlo steps (device-drawn lists, sorted on the device) equals the eager path
+    from gpu_util import as_input, make_ctx
+    eps = 1e-7 if dtype == 0 else 1e-4
+    psi = as_input(synth.haar_state(n, 2600 + n), dtype)
+    rng = np.random.default_rng(2600 + n)
+    xs = np.concatenate([rng.integers(1, 1 << n, size=23, dtype=np.uint64),
+                         np.array([0, 1, 3, 1 << 20, (1 << n) - 1], dtype=np.uint64)])
+    rng.shuffle(xs)
+    log("grouped list n=%d dtype=%d nx=%d" % (n, dtype, len(xs)))
+    ctx = make_ctx(psi, dtype)
+    g = ctx.eval_x(xs, eps)
+    mc = []
+    for graphs in (0, 1):
+        log("grouped Monte Carlo n=%d dtype=%d graphs=%d" % (n, dtype, graphs))
+        pw.pw_set_graphs(ctx.h, graphs)
+        mc.append(ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, eps, 16, 49, 0.0, 31))
+    ctx.close()
+    log("ungrouped list n=%d dtype=%d" % (n, dtype))
+    ctx1 = make_ctx(psi, dtype, x_batch=1)
+    g1 = ctx1.eval_x(xs, eps)
+    ctx1.close()
+    assert np.array_equal(g["x"], xs)
+    assert np.array_equal(g.view(np.uint8), g1.view(np.uint8))
+    for k in ("M", "M_se", "S", "M1", "n_samples"):
+        assert np.array_equal(np.asarray(mc[0][k]), np.asarray(mc[1][k])), k
+    sel = [0, 5, 11, len(xs) - 1]
+    r = oracle.eval_x(psi, xs[sel], eps=eps, max_alpha=4)
+    for j, i in enumerate(sel):
+        if dtype == pw.PW_C128:
+            assert abs(g["m"][i, 0] / r["m"][j, 0] - 1) < 1e-10
+            assert abs(g["p"][i] / r["p"][j] - 1) < 1e-10
+        else:
+            b = family_bounds(oracle.spectrum(psi, int(xs[i])), n)
+            assert abs(g["m"][i, 0] - r["m"][j, 0]) <= b["m2"]
+            assert abs(g["p"][i] - r["p"][j]) <= b["p"]
+        assert int(g["nu"][i]) == int(r["nu"][j])
