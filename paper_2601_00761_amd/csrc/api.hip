@@ -134,9 +134,9 @@ int default_batch(int n, pw_dtype dt) {
     // power of two
     size_t p = 1;
     while (p * 2 <= b) p *= 2;
-    // states the caches do not hold: launches of four families, which the first pass
-    // runs in one tile-sharing group (up to 16 GiB of half spectra)
-    while (p < 4 && first_pass_group(n, dt == PW_C128, 4) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
+    // states of 16 MiB and more: launches of at least four families, which the first
+    // pass runs in one tile-sharing group (up to 16 GiB of half spectra)
+    while (p < 4 && first_pass_group(P, dt == PW_C128, 4) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
     return (int)p;
 }
 
@@ -349,7 +349,7 @@ pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, 
 pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
                          hipStream_t st) {
     if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
-    if (!d_xs || c->P.fused || first_pass_group(c->n, c->dtype == PW_C128, c->run_batch) < 2)
+    if (!d_xs || first_pass_group(c->P, c->dtype == PW_C128, c->run_batch) < 2)
         return eval_list_on(c, d_xs, x0, nx, eps, d_out, st);
     // tile-sharing groups: the list is evaluated in top-bit order, so that the families
     // of a launch share state tiles, and the results are put back in list order

@@ -59,9 +59,10 @@ struct Plan {
 Plan make_plan(int n, bool dbl);
 
 // Families per group of the first pass that share their state tiles (1, 2 or 4; more
-// than 1 only for states of 512 MiB and more, and at most nb).  The workgroups of one
-// tile and group run back to back on one XCD, so the tile comes from HBM once.
-int first_pass_group(int n, bool dbl, int nb);
+// than 1 only for multi-pass plans of states of 16 MiB and more, and at most nb).  The
+// workgroups of one tile and group run back to back on one XCD, so the tile leaves
+// HBM (or the MALL) once.
+int first_pass_group(const Plan& P, bool dbl, int nb);
 
 // Grouping support for lists of families: a stable sort of nx <= SORT_MAX families by
 // the top set bit of x mod 2^n (x = 0 first), xs_sorted[j] = xs[perm[j]], so that

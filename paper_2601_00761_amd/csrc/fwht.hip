@@ -822,11 +822,11 @@ k_fused_store(const cx<R>* __restrict__ psi, int n, uint64_t x, cx<R>* __restric
 // First pass of a multi-pass transform: products + low K index bits of one tile.
 // HSRC: the values come from the family-major reduced density matrix of the mixed-state
 // path (psi is D and n is n_a) instead of products of the state.
-// Grid: (tiles per family, families), or with GRP > 1 (states beyond the caches, families
-// in groups of GRP with the same top bit of x, hence the same state tile): one dimension
+// Grid: (tiles per family, families), or with GRP > 1 (states of 16 MiB and more, families
+// in groups of GRP with the same top bit of x, hence the same state tiles): one dimension
 // of tiles x ceil(nb / GRP) GRP workgroups, numbered so that the GRP workgroups of one
 // tile and group follow each other on one XCD (workgroups are dealt round-robin to the 8
-// XCDs): the first reads the tile from HBM, the others find it in that XCD's L2.
+// XCDs): the first reads the tile from HBM or the MALL, the others find it in that XCD's L2.
 // Requires tiles % 8 == 0; workgroups of the padding slots (>= nb) return at once.
 template <typename R, int TL, int RL, bool SPLIT = false, bool HSRC = false, int GRP = 1>
 __global__ void __launch_bounds__(1 << TL)
@@ -1300,7 +1300,7 @@ template <typename R, int TL, int RL, bool SPLIT>
 void launch_first(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, void* work,
                   hipStream_t st, const LaunchTimer* tm) {
     const uint32_t tiles = 1u << (P.nh - TL - RL);
-    const int grp = first_pass_group(P.n, sizeof(R) == 8, nb);
+    const int grp = first_pass_group(P, sizeof(R) == 8, nb);
     const uint32_t blocks = tiles * (uint32_t)((nb + grp - 1) / grp * grp);
     if (grp == 4)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 4>), dim3(blocks), dim3(1 << TL), st,
@@ -1528,9 +1528,10 @@ hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, 
                           : launch_reduced<float, 2>(rho, na, x0, nb, (float)eps, out, st);
 }
 
-int first_pass_group(int n, bool dbl, int nb) {
-    // states of 512 MiB and more: the caches do not hold the state between families
-    if (((size_t)(dbl ? 16 : 8) << n) < ((size_t)512 << 20)) return 1;
+int first_pass_group(const Plan& P, bool dbl, int nb) {
+    // states of 16 MiB and more (measured: 4-21 % less time per family from 16 MiB to
+    // 8 GiB); at least 8 tiles per family, which the grouped numbering needs
+    if (P.fused || P.nh - P.k1 < 3 || ((size_t)(dbl ? 16 : 8) << P.n) < ((size_t)16 << 20)) return 1;
     return nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
 }
 

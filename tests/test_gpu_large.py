@@ -194,9 +194,9 @@ def test_signed_family_values_largest(n, dtype):
     ctx.close()
 
 
-@pytest.mark.parametrize("n,dtype", [(26, 1), (25, 0)])
+@pytest.mark.parametrize("n,dtype", [(26, 1), (25, 0), (21, 1), (20, 0)])
 def test_tile_sharing_groups_keep_list_order_and_values(n, dtype):
-    # states of 512 MiB and more evaluate a list in top-bit order, four families per
+    # states of 16 MiB and more evaluate a list in top-bit order, four families per
     # launch sharing their state tiles, and put the results back in list order.  A ragged
     # unsorted list with mixed top bits gives bitwise the results of one family per launch
     # (no groups, no sorting); sampled families agree with the oracle; graph replay of
@@ -206,7 +206,7 @@ def test_tile_sharing_groups_keep_list_order_and_values(n, dtype):
     psi = as_input(synth.haar_state(n, 2600 + n), dtype)
     rng = np.random.default_rng(2600 + n)
     xs = np.concatenate([rng.integers(1, 1 << n, size=23, dtype=np.uint64),
-                         np.array([0, 1, 3, 1 << 20, (1 << n) - 1], dtype=np.uint64)])
+                         np.array([0, 1, 3, 1 << (n - 3), (1 << n) - 1], dtype=np.uint64)])
     rng.shuffle(xs)
     log("grouped list n=%d dtype=%d nx=%d" % (n, dtype, len(xs)))
     ctx = make_ctx(psi, dtype)
