@@ -236,3 +236,35 @@ def test_tile_sharing_groups_keep_list_order_and_values(n, dtype):
             assert abs(g["m"][i, 0] - r["m"][j, 0]) <= b["m2"]
             assert abs(g["p"][i] - r["p"][j]) <= b["p"]
         assert int(g["nu"][i]) == int(r["nu"][j])
+
+
+@pytest.mark.parametrize("n,dtype,xb", [(21, 1, 2), (21, 1, 8), (20, 0, 8)])
+def test_tile_sharing_group_sizes_and_padding(n, dtype, xb):
+    # a lent workspace fixes the launch: two families (groups of two; an odd list ends
+    # with a single family), or eight (two groups of four; a 29-family list ends with a
+    # launch of five, padded to two groups whose unused workgroups return at once).  A
+    # device list of 4099 families crosses the 4096-family staging of the sort.  All
+    # bitwise equal to one family per launch.
+    import torch
+    from gpu_util import as_input, make_ctx
+    eps = 1e-7 if dtype == 0 else 1e-4
+    psi = as_input(synth.haar_state(n, 2700 + n), dtype)
+    rng = np.random.default_rng(2700 + n + xb)
+    xs = rng.integers(0, 1 << n, size=29, dtype=np.uint64)
+    log("group sizes n=%d dtype=%d x_batch=%d" % (n, dtype, xb))
+    ctx1 = make_ctx(psi, dtype, x_batch=1)
+    ctx = make_ctx(psi, dtype, x_batch=xb)
+    ref, got = ctx1.eval_x(xs, eps), ctx.eval_x(xs, eps)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+    if xb == 8:
+        big = rng.integers(0, 1 << n, size=4099, dtype=np.uint64)
+        log("device list of %d families n=%d dtype=%d" % (len(big), n, dtype))
+        d_xs = torch.from_numpy(big.view(np.int64)).to("cuda:0")
+        d_out = torch.zeros(len(big) * pw.XRES_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+        pw.pw_eval_x_device(ctx.h, d_xs, len(big), eps, d_out)
+        torch.cuda.synchronize()
+        got_big = d_out.cpu().numpy().view(pw.XRES_DTYPE)
+        ref_big = ctx1.eval_x(big, eps)
+        assert np.array_equal(got_big.view(np.uint8), ref_big.view(np.uint8))
+    ctx.close()
+    ctx1.close()
