@@ -153,7 +153,7 @@ MC_BATCH = 64
 def mc_leg(pw, torch, stream, eta, timing_every):
     """M_2 wall time at fixed standard error: an N = 28 T-doped Clifford state (eta Cliffords
     per T, N_T = 2N = 56, complex64), Clifford preconditioning with 2N brick-wall layers,
-    then x drawn from the exact marginal (plus x = 0), 64 per batch, until the standard
+    then x drawn from the exact marginal (plus x = 0), 64 per launch, until the standard
     error of M_2 is 1e-3 or 16384 families.  Timed: preconditioning + sampling + evaluation.
     State preparation (the T-doped circuit itself) is input generation and is not timed."""
     import numpy as np
@@ -165,7 +165,9 @@ def mc_leg(pw, torch, stream, eta, timing_every):
     psi0[0] = 1.0
     ctx = pw.Context(0, stream)
     pw.pw_set_moments(ctx.h, 2)
-    ctx.upload(psi0, pw.PW_C64)
+    # a lent workspace for the step's 64 families (64 GiB of half spectra): each step is one
+    # launch of each pass (the library's own default launches four families at this size)
+    ctx.upload(psi0, pw.PW_C64, x_batch=MC_BATCH)
     del psi0
     ctx.apply_gates(kinds, qubits, mats)
     torch.cuda.synchronize()
@@ -207,7 +209,7 @@ def mc_leg(pw, torch, stream, eta, timing_every):
                    + t_col / kt["k_column(last)"]["families_per_launch"])
     copy = copy_ceiling(torch)
     return {"workload": "N=%d T-doped Clifford state, eta=%d, N_T=%d, complex64; Clifford preconditioning %d "
-                        "brick-wall layers; x ~ exact marginal (x != 0) plus x = 0, %d per batch; stop at "
+                        "brick-wall layers; x ~ exact marginal (x != 0) plus x = 0, %d per launch; stop at "
                         "std-err(M_2) <= %g or %d families" % (n, eta, 2 * n, 2 * n, MC_BATCH, MC_TARGET_SE, MC_MAX),
             "eta": eta, "M2": res["M"][0], "M2_se": res["M_se"][0], "M1": res["M1"], "M1_se": res["M1_se"],
             "r2": res["r"][0], "n_samples": fams, "target_reached": bool(res["M_se"][0] <= MC_TARGET_SE),
