@@ -60,9 +60,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, summary="pmc_traffic_c64_n20.json"):
-    """HBM traffic per launch from a committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel source (else None)."""
+def load_traffic(kernel, summary="pmc_traffic_c64_n20.json", field="hbm_bytes_per_launch"):
+    """HBM traffic per launch (or per family, where the summary records the families of
+    the profiled launches) from a committed rocprofv3 --pmc summary, if it was taken on
+    the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
@@ -73,7 +74,7 @@ def load_traffic(kernel, summary="pmc_traffic_c64_n20.json"):
     k = d.get("kernels", {}).get(kernel)
     if not k:
         return None
-    return k.get("hbm_bytes_per_launch")
+    return k.get(field)
 
 
 def fill_ceiling(torch, nbytes=256 << 20, reps=20):
@@ -201,12 +202,9 @@ def mc_leg(pw, torch, stream, eta, timing_every):
     per_fam_us = sum(v["avg_us"] / v["families_per_launch"] for v in kt.values())
     alg = float(1 << n) * 8.0
     # counter-measured bytes per family of the two kernels (first pass, reducing column pass)
-    t_first = load_traffic("k_first", "pmc_traffic_c64_n28_mc.json")
-    t_col = load_traffic("k_column", "pmc_traffic_c64_n28_mc.json")
-    traffic = None
-    if t_first is not None and t_col is not None and "k_first" in kt and "k_column(last)" in kt:
-        traffic = (t_first / kt["k_first"]["families_per_launch"]
-                   + t_col / kt["k_column(last)"]["families_per_launch"])
+    t_first = load_traffic("k_first", "pmc_traffic_c64_n28_mc.json", "hbm_bytes_per_family")
+    t_col = load_traffic("k_column", "pmc_traffic_c64_n28_mc.json", "hbm_bytes_per_family")
+    traffic = t_first + t_col if t_first is not None and t_col is not None else None
     copy = copy_ceiling(torch)
     return {"workload": "N=%d T-doped Clifford state, eta=%d, N_T=%d, complex64; Clifford preconditioning %d "
                         "brick-wall layers; x ~ exact marginal (x != 0) plus x = 0, %d per launch; stop at "
