@@ -92,17 +92,25 @@ def test_psi_m_closed_forms_largest_sizes(n):
 
 
 def test_scrambled_psi_m_monte_carlo_n28():
-    # M_2(C psi_m) = M_2(psi_m) = (N/2) log2(4/3): preconditioning, marginal sampling and the estimator at full size
+    # M_2(C psi_m) = M_2(psi_m) = (N/2) log2(4/3): preconditioning, marginal sampling and the
+    # estimator at full size, with the library's default launches and with the benchmark's
+    # lent workspace of 64 families (one launch per 64-draw step): the same numbers
     n = 28
     psi = psi_m_sparse(n)
     k, q, m = synth.gates_to_arrays(synth.random_brickwall_clifford(n, 2 * n, synth.SEED_BASE + 28))
-    log("scrambled psi_m MC n=%d gates=%d" % (n, len(k)))
-    ctx = pw.Context(0)
-    ctx.upload(psi, pw.PW_C64)
-    del psi
-    ctx.apply_gates(k, q, m)
-    res = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 64, 4097, 2e-3, 7)
-    ctx.close()
+    out = []
+    for x_batch in (None, 64):
+        log("scrambled psi_m MC n=%d gates=%d x_batch=%s" % (n, len(k), x_batch))
+        ctx = pw.Context(0)
+        ctx.upload(psi, pw.PW_C64, x_batch=x_batch)
+        ctx.apply_gates(k, q, m)
+        pw.pw_set_graphs(ctx.h, 1)
+        out.append(ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 64, 4097, 2e-3, 7))
+        ctx.close()
+        del ctx
+    for key in ("M", "M_se", "S", "n_samples", "M1"):
+        assert np.array_equal(np.asarray(out[0][key]), np.asarray(out[1][key])), key
+    res = out[0]
     exact = (n // 2) * math.log2(4 / 3)
     log("M2 = %.5f +- %.5f (exact %.5f), n_samples=%d" % (res["M"][0], res["M_se"][0], exact, res["n_samples"]))
     assert res["M_se"][0] < 0.02
