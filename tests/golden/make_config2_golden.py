@@ -1,0 +1,104 @@
+"""Write the exact-enumeration reference values of the N = 20 T-doped Clifford workload.
+
+Calls only the FP64 CPU oracle (Algorithm 1 over all 2^20 X-bitstrings) and the input
+generators.  The state is |0...0> followed by the T-doped gate stream (two-qubit
+Cliffords uniform over the 11520-element group in brick-wall order, one T on a random
+qubit after every eta = 20 of them, N_T = 20 T gates; seed SEED_BASE + 2), applied by
+the oracle's own gate loop in FP64.  Two entries are written:
+
+  c128: that state, nullity tolerance 1e-7 (Algorithm 1);
+  c64:  the same state rounded to complex64 and widened back to complex128 (the exact
+        input of a complex64 run), nullity tolerance 1e-4 (the single-precision
+        reading of the tolerance).
+
+Each entry records S_2..4 = sum_x m_{alpha;x}, L = sum_x sum_z |F|^2 log2 |F|^2,
+P = sum_x p(x), nu_cnt, the largest gap over families, the derived M_1, M_2..4 and
+the nullity, and a SHA-256 of the state bytes so that a test can check that it
+rebuilt the same input.
+
+About two hours per entry on eight cores.  Run from the repository root:
+    python tests/golden/make_config2_golden.py [c128|c64 ...]
+"""
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+OUT = os.path.join(ROOT, "tests", "golden", "config2_n20_tdoped.json")
+N, ETA, N_T = 20, 20, 20
+SEED = synth.SEED_BASE + 2
+
+
+def config2_state():
+    """The N = 20 T-doped Clifford state in complex128 (oracle gate loop)."""
+    kinds, qubits, mats = synth.gates_to_arrays(synth.tdoped_stream(N, ETA, N_T, SEED))
+    psi0 = np.zeros(1 << N, dtype=np.complex128)
+    psi0[0] = 1.0
+    return oracle.apply_gates(psi0, kinds, qubits, mats)
+
+
+def state_variant(psi128, kind):
+    if kind == "c128":
+        return psi128
+    return psi128.astype(np.complex64)
+
+
+def sha256(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def entry(kind):
+    psi = state_variant(config2_state(), kind)
+    eps = 1e-7 if kind == "c128" else 1e-4
+    t0 = time.time()
+    r = oracle.alg1(psi.astype(np.complex128), eps=eps, max_alpha=4, per_x=True)
+    px = r["per_x"]
+    return {
+        "state_sha256": sha256(psi),
+        "dtype": kind,
+        "eps": eps,
+        "S": [float(v) for v in r["S"]],
+        "L": r["L"],
+        "P": r["P"],
+        "nu_cnt": int(r["nu_cnt"]),
+        "gap_max": float(np.max(px["gap"])),
+        "M": {str(a): r["M"][a] for a in (2, 3, 4)},
+        "M1": r["M1"],
+        "nullity": r["nu"],
+        "oracle_seconds": round(time.time() - t0, 1),
+    }
+
+
+def main(kinds):
+    data = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            data = json.load(f)
+    data["_about"] = ("Algorithm 1 (FP64 CPU oracle) over all 2^20 X-bitstrings of the N = 20 T-doped Clifford "
+                      "state (eta = 20, N_T = 20, from |0...0>, seed SEED_BASE + 2); written by "
+                      "tests/golden/make_config2_golden.py, which calls only oracle/ and synth/.")
+    for k in kinds:
+        print("computing", k, flush=True)
+        data[k] = entry(k)
+        print(json.dumps(data[k]), flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+            f.write("\n")
+
+
+if __name__ == "__main__":
+    ks = sys.argv[1:] or ["c128", "c64"]
+    for k in ks:
+        if k not in ("c128", "c64"):
+            raise SystemExit("unknown entry %r" % k)
+    main(ks)

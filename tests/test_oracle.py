@@ -169,6 +169,29 @@ def test_T_on_stabilizer_product_additivity(n, seed):
     assert (r["nu_cnt"] & (r["nu_cnt"] - 1)) == 0  # a group order: power of two
 
 
+def test_gap_closed_form_for_t_states():
+    # Algorithm 1's nullity test with the margin reported beside it: gap_x is the largest
+    # |c| of family x that lies below 1 - eps.  For |T> the Bloch values are 1 (I), 1/sqrt2
+    # (X, Y), 0 (Z): the family x = 0 holds {1, 0} (gap 0: the 1 is counted by the nullity
+    # test, not the gap) and x = 1 holds {1/sqrt2, 1/sqrt2}.
+    r = oracle.eval_x(synth.T_STATE, np.array([0, 1]))
+    assert r["gap"][0] == 0.0 and r["nu"][0] == 1
+    assert abs(r["gap"][1] - 1 / math.sqrt(2)) < 1e-15 and r["nu"][1] == 0
+    # psi_m = |T>^k |0>^(n-k): |c| factorises over qubits, so family x with no x bit on the
+    # |0> qubits and j >= 1 bits on the T qubits takes the values {2^(-j/2), 0}; every other
+    # family has gap 0 (all values 0, or {1, 0} for x = 0)
+    n, k = 6, 4
+    psi = synth.psi_m_state(n, k)
+    r = oracle.eval_x(psi, np.arange(1 << n))
+    for x in range(1 << n):
+        j = bin(x & ((1 << k) - 1)).count("1")
+        want = 2.0 ** (-j / 2) if (x >> k) == 0 and j >= 1 else 0.0
+        assert abs(r["gap"][x] - want) < 1e-14, (x, r["gap"][x], want)
+    # a stabilizer state has no value strictly between 0 and 1: gap 0 everywhere
+    r = oracle.eval_x(_random_clifford_state(5, 15, 61), np.arange(32))
+    assert np.all(np.abs(r["gap"]) < 1e-12)
+
+
 def test_clifford_invariance_of_magic_and_nullity():
     n = 6
     labels = synth.stabilizer_product_spec(n, 51)
@@ -357,6 +380,102 @@ def test_marginal_estimator_is_unbiased_and_exact_for_alpha1():
         assert abs(S1 - 1) < 1e-12 and se1 < 1e-12
     ests = np.array(ests)
     assert abs(ests.mean() - S) < 5 * ests.std() / math.sqrt(len(ests))
+
+
+def test_standard_error_two_point_closed_form():
+    # Eq. stdM on a sample of two: the sample sd (n - 1) of {a, b} is |a - b|/sqrt(2), so the
+    # standard error of the mean is |a - b|/2; sigma_M = sigma_S / (|1 - alpha| ln 2 S)
+    a, b, s0 = 3.0, 7.0, 0.5
+    for alpha in (2, 3, 4):
+        S, se, sM = oracle.mc_estimate([a, b], s0, alpha)
+        assert S == s0 + 5.0
+        assert abs(se - 2.0) < 1e-15
+        assert abs(sM - 2.0 / ((alpha - 1) * math.log(2.0) * 5.5)) < 1e-15
+    # three equal terms: no spread
+    S, se, sM = oracle.mc_estimate([4.0, 4.0, 4.0], 1.0, 2)
+    assert S == 5.0 and se == 0.0 and sM == 0.0
+
+
+def _var_band(v, z=5.0):
+    # z standard errors of the sample variance of v: sqrt((mu_4 - sigma^4) / len(v))
+    c = v - v.mean()
+    s2 = np.mean(c ** 2)
+    return z * math.sqrt((np.mean(c ** 4) - s2 * s2) / len(v))
+
+
+def _exact_uniform_spread(n, m2):
+    # per-draw term y = (d - 1) m_x with x uniform over x != 0: exact mean and variance
+    d = 1 << n
+    y = (d - 1.0) * m2[1:]
+    return y.mean(), y.var()
+
+
+def test_uniform_standard_error_is_calibrated():
+    # Monte Carlo section, Eq. stdM: the reported standard error squared is an unbiased
+    # estimate of Var(S_hat) = Var(y)/k for k i.i.d. draws (sample variance with k - 1), and
+    # the estimates themselves scatter with that variance.  With k = 5 a population variance
+    # (k instead of k - 1) would be 20 % low, far outside the bands below.
+    n, k, reps = 7, 5, 4000
+    psi = synth.haar_state(n, 93)
+    m2 = oracle.eval_x(psi, np.arange(1 << n))["m"][:, 0]
+    mu, var = _exact_uniform_spread(n, m2)
+    ests, se2 = [], []
+    for s in range(reps):
+        xs = oracle.sample_uniform_nz(n, 30000 + s, 0, k).astype(np.int64)
+        S, se, _ = oracle.mc_uniform(n, m2[0], m2[xs], 2)
+        ests.append(S)
+        se2.append(se * se)
+    ests, se2 = np.array(ests), np.array(se2)
+    target = var / k
+    # mean of the reported se^2 against the exact Var(S_hat)
+    assert abs(se2.mean() - target) < 5 * se2.std() / math.sqrt(reps)
+    # empirical variance of the estimates against Var(S_hat): a 5-sigma band from their
+    # own fourth moment (the sampling error of a sample variance)
+    assert abs(ests.var(ddof=1) - target) < _var_band(ests)
+    assert abs(ests.mean() - (m2[0] + mu)) < 5 * math.sqrt(target / reps)
+
+
+def test_marginal_standard_error_is_calibrated():
+    # the same calibration for the importance-sampled estimator: y = (1 - p0) m_x / p(x),
+    # x ~ p(x | x != 0), exact Var(y) from the full table
+    n, k, reps = 6, 5, 3000
+    psi = _random_clifford_state(n, 4, 97)
+    psi = oracle.apply_gates(psi, *synth.gates_to_arrays([synth.t_gate(j) for j in range(n)]))
+    r = oracle.eval_x(psi, np.arange(1 << n))
+    m2, p = r["m"][:, 0], r["p"]
+    w = p[1:] / (1.0 - p[0])
+    y = (1.0 - p[0]) * m2[1:] / np.where(p[1:] > 0, p[1:], 1.0)
+    mu = np.sum(w * y)
+    var = np.sum(w * (y - mu) ** 2)
+    ests, se2 = [], []
+    for s in range(reps):
+        xs, failed = oracle.sample_marginal_nz(psi, 40000 + s, 0, k)
+        assert failed == 0
+        xi = xs.astype(np.int64)
+        S, se, _ = oracle.mc_marginal(m2[0], p[0], m2[xi], p[xi], 2)
+        ests.append(S)
+        se2.append(se * se)
+    ests, se2 = np.array(ests), np.array(se2)
+    target = var / k
+    assert abs(se2.mean() - target) < 5 * se2.std() / math.sqrt(reps)
+    assert abs(ests.var(ddof=1) - target) < _var_band(ests)
+
+
+def test_sigma_M_delta_method_matches_the_scatter_of_M():
+    # sigma_M = sigma_S / (ln 2 S) (alpha = 2): the reported sigma_M agrees with the spread
+    # of M_hat over independent runs (a missing ln 2 would be 44 % off, a missing sqrt(k)
+    # a factor sqrt(k))
+    n, k, reps = 7, 64, 600
+    psi = synth.haar_state(n, 99)
+    m2 = oracle.eval_x(psi, np.arange(1 << n))["m"][:, 0]
+    Ms, sMs = [], []
+    for s in range(reps):
+        xs = oracle.sample_uniform_nz(n, 50000 + s, 0, k).astype(np.int64)
+        S, _, sM = oracle.mc_uniform(n, m2[0], m2[xs], 2)
+        Ms.append(oracle.M_from_S(n, S, 2))
+        sMs.append(sM)
+    ratio = np.std(Ms, ddof=1) / np.mean(sMs)
+    assert 0.85 < ratio < 1.15, ratio
 
 
 @pytest.mark.slow

@@ -72,6 +72,26 @@ def test_adam_first_step_is_signed_lr():
     assert np.max(np.abs(p - ref)) < 1e-15
 
 
+def test_adam_three_steps_by_hand():
+    # Adam (Kingma & Ba 2015) over three steps with gradients g, -g, g (g = 1/2, lr = 0.01):
+    #   m_1 = 0.05, m_2 = 0.9 m_1 - 0.05 = -0.005, m_3 = 0.9 m_2 + 0.05 = 0.0455;
+    #   v_t = (1 - 0.999^t) g^2, so the bias-corrected second moment is g^2 at every step;
+    #   bias-corrected first moments 0.05/0.1 = 1/2, -0.005/0.19 = -1/38, 0.0455/0.271 = 91/542;
+    #   steps lr m_hat / |g| = lr, -lr/19, lr 91/271 (eps = 1e-8 moves them by < 1e-9).
+    lr = 0.01
+    p = np.zeros(2)
+    m = np.zeros(2)
+    v = np.zeros(2)
+    for t, g in enumerate((0.5, -0.5, 0.5), start=1):
+        p, m, v = made.adam_step(p, np.array([g, -g]), m, v, t, lr)
+        if t == 2:
+            assert abs(p[0] - (-lr * (1 - 1 / 19))) < 1e-9 and abs(m[0] + 0.005) < 1e-15
+    want = -lr * (1 - 1 / 19 + 91 / 271)
+    assert abs(p[0] - want) < 1e-9 and abs(p[1] + want) < 1e-9
+    assert abs(m[0] - 0.0455) < 1e-15
+    assert abs(v[0] - 0.25 * (1 - 0.999 ** 3)) < 1e-17
+
+
 def test_sampler_law_chi2():
     n, h = 4, 8
     p = synth.made_init(n, h, 21)
