@@ -42,6 +42,8 @@ def lib():
         L.pwo_bruteforce.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.pwo_eval_x.argtypes = [ctypes.c_int, _dp, _u64p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                  _dp, _dp, _dp, _u64p, _dp]
+        L.pwo_eval_x_sums.argtypes = [ctypes.c_int, _dp, _u64p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                      _dp, _dp, _dp, _u64p, _dp, _dp]
         L.pwo_spectrum.argtypes = [ctypes.c_int, _dp, ctypes.c_uint64, _dp]
         L.pwo_alg1.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp, _u64p,
                                _dp, _dp, _dp, _u64p, _dp]
@@ -116,6 +118,23 @@ def eval_x(psi, xs, eps=1e-7, max_alpha=4):
                           out["p"].ctypes.data_as(_dp), out["ent"].ctypes.data_as(_dp),
                           out["m"].ctypes.data_as(_dp), out["nu"].ctypes.data_as(_u64p),
                           out["gap"].ctypes.data_as(_dp)))
+    return out
+
+
+def eval_x_with_bound_sums(psi, xs, eps=1e-7, max_alpha=4):
+    """eval_x plus, per x, six sums over z of the same spectrum (key "bsum", shape [nx, 6]):
+    sum |F|, |F|^3, |F|^5, |F|^7, |2|F| log2|F|^2 + 2|F|/ln 2|, ||F|^2 log2 |F|^2|.  They size the
+    first-order rounding bounds of a reduced-precision evaluation of the family (tests)."""
+    a, p = _c128(psi)
+    n = _nq(a)
+    xs = np.ascontiguousarray(xs, dtype=np.uint64)
+    nx = len(xs)
+    out = dict(p=np.empty(nx), ent=np.empty(nx), m=np.empty((nx, max_alpha - 1)),
+               nu=np.empty(nx, dtype=np.uint64), gap=np.empty(nx), bsum=np.empty((nx, 6)))
+    _chk(lib().pwo_eval_x_sums(n, p, xs.ctypes.data_as(_u64p), nx, float(eps), int(max_alpha),
+                               out["p"].ctypes.data_as(_dp), out["ent"].ctypes.data_as(_dp),
+                               out["m"].ctypes.data_as(_dp), out["nu"].ctypes.data_as(_u64p),
+                               out["gap"].ctypes.data_as(_dp), out["bsum"].ctypes.data_as(_dp)))
     return out
 
 

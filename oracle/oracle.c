@@ -139,6 +139,10 @@ typedef struct {
     double m[7];     /* m_{alpha;x} for alpha = 2..8                    */
     uint64_t nu;     /* #{z : ||F| - 1| < eps}                           */
     double gap;      /* max{|F| : |F| < 1 - eps}, -1 if none            */
+    /* sums over z that size first-order rounding bounds of a reduced-precision
+     * evaluation of the same family (not part of Algorithm 1):
+     * sum |F|, |F|^3, |F|^5, |F|^7, |2|F| log2|F|^2 + 2|F|/ln 2|, ||F|^2 log2 |F|^2| */
+    double bsum[6];
 } xres;
 
 /* Reductions of Algorithm 1 over one spectrum F_x (nullity count, partial
@@ -150,10 +154,13 @@ static void reduce_spectrum(const cplx* F, int n, double eps, int max_alpha, xre
     memset(sm, 0, sizeof sm);
     uint64_t nu = 0;
     double gap = -1.0;
+    nsum sb[6];
+    memset(sb, 0, sizeof sb);
     #pragma omp parallel if (par)
     {
-        nsum lp = {0, 0}, le = {0, 0}, lm[7];
+        nsum lp = {0, 0}, le = {0, 0}, lm[7], lb[6];
         memset(lm, 0, sizeof lm);
+        memset(lb, 0, sizeof lb);
         uint64_t lnu = 0;
         double lgap = -1.0;
         #pragma omp for schedule(static) nowait
@@ -166,15 +173,25 @@ static void reduce_spectrum(const cplx* F, int n, double eps, int max_alpha, xre
             if (a2 > 0.0) nadd(&le, a2 * log2(a2));
             double pw = a2;
             for (int al = 2; al <= max_alpha; ++al) { pw *= a2; nadd(&lm[al - 2], pw); }
+            nadd(&lb[0], a);
+            nadd(&lb[1], a * a2);
+            nadd(&lb[2], a * a2 * a2);
+            nadd(&lb[3], a * a2 * a2 * a2);
+            if (a2 > 0.0) {
+                nadd(&lb[4], fabs(2.0 * a * log2(a2) + 2.0 * a / log(2.0)));
+                nadd(&lb[5], fabs(a2 * log2(a2)));
+            }
         }
         #pragma omp critical
         {
             nadd(&sp, nval(&lp)); nadd(&se, nval(&le));
             for (int al = 2; al <= max_alpha; ++al) nadd(&sm[al - 2], nval(&lm[al - 2]));
+            for (int k = 0; k < 6; ++k) nadd(&sb[k], nval(&lb[k]));
             nu += lnu;
             if (lgap > gap) gap = lgap;
         }
     }
+    for (int k = 0; k < 6; ++k) r->bsum[k] = nval(&sb[k]);
     r->p = ldexp(nval(&sp), -n);
     r->ent = nval(&se);
     for (int al = 2; al <= 8; ++al) r->m[al - 2] = (al <= max_alpha) ? ldexp(nval(&sm[al - 2]), -n * al) : 0.0;
@@ -185,8 +202,8 @@ static void reduce_spectrum(const cplx* F, int n, double eps, int max_alpha, xre
 /* Per-family results for a list of x (the per-family steps of Algorithm 1: product,
  * transform, nullity count and moments, plus the Shannon term).  Outputs are arrays of length nx; m has nx*(max_alpha-1)
  * entries, alpha-major within each x. */
-PWO_EXPORT int pwo_eval_x(int n, const double* psi_in, const uint64_t* xs, int64_t nx, double eps,
-                          int max_alpha, double* p, double* ent, double* m, uint64_t* nu, double* gap) {
+static int eval_x_impl(int n, const double* psi_in, const uint64_t* xs, int64_t nx, double eps,
+                       int max_alpha, double* p, double* ent, double* m, uint64_t* nu, double* gap, double* bsum) {
     if (n < 1 || n > 34 || !psi_in || !xs || nx < 0 || max_alpha < 2 || max_alpha > 8) return -1;
     const uint64_t d = 1ull << n;
     for (int64_t i = 0; i < nx; ++i) if (xs[i] >= d) return -1;
@@ -207,6 +224,7 @@ PWO_EXPORT int pwo_eval_x(int n, const double* psi_in, const uint64_t* xs, int64
                 if (m) for (int al = 2; al <= max_alpha; ++al) m[i * (max_alpha - 1) + (al - 2)] = r.m[al - 2];
                 if (nu) nu[i] = r.nu;
                 if (gap) gap[i] = r.gap;
+                if (bsum) memcpy(bsum + 6 * i, r.bsum, sizeof r.bsum);
             }
             free(f);
         }
@@ -223,10 +241,26 @@ PWO_EXPORT int pwo_eval_x(int n, const double* psi_in, const uint64_t* xs, int64
             if (m) for (int al = 2; al <= max_alpha; ++al) m[i * (max_alpha - 1) + (al - 2)] = r.m[al - 2];
             if (nu) nu[i] = r.nu;
             if (gap) gap[i] = r.gap;
+            if (bsum) memcpy(bsum + 6 * i, r.bsum, sizeof r.bsum);
         }
         free(f);
     }
     return 0;
+}
+
+PWO_EXPORT int pwo_eval_x(int n, const double* psi_in, const uint64_t* xs, int64_t nx, double eps,
+                          int max_alpha, double* p, double* ent, double* m, uint64_t* nu, double* gap) {
+    return eval_x_impl(n, psi_in, xs, nx, eps, max_alpha, p, ent, m, nu, gap, NULL);
+}
+
+/* pwo_eval_x plus, per x, the six sums of xres.bsum (6 doubles per x in bsum), from the
+ * same transform: what first-order rounding bounds of a reduced-precision evaluation of
+ * the family need. */
+PWO_EXPORT int pwo_eval_x_sums(int n, const double* psi_in, const uint64_t* xs, int64_t nx, double eps,
+                               int max_alpha, double* p, double* ent, double* m, uint64_t* nu, double* gap,
+                               double* bsum) {
+    if (!bsum) return -1;
+    return eval_x_impl(n, psi_in, xs, nx, eps, max_alpha, p, ent, m, nu, gap, bsum);
 }
 
 /* The raw transform F_x(z) for one x (complex, length 2^n). */

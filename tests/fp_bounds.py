@@ -38,3 +38,19 @@ def family_bounds(F, n):
     out["ent"] = g * np.sum(np.abs(2 * a * lg + 2 * a / math.log(2))) + acc * np.sum(np.abs(a * a * lg))
     out["gamma"] = g
     return out
+
+
+def family_bounds_from_sums(r, i, n):
+    """The same bounds from the oracle's per-family sums (oracle.eval_x_with_bound_sums,
+    family i): no spectrum needs to be held in the test."""
+    b = r["bsum"][i]
+    d = float(2 ** n)
+    g = gamma(n)
+    acc = 32 * U32
+    out = {"gamma": g}
+    out["p"] = 2 * g * b[0] / d + acc * r["p"][i]
+    for k, al in enumerate((2, 3, 4)):
+        out["m%d" % al] = 2 * al * g * b[1 + k] / d ** al + acc * al * r["m"][i, k]
+    out["ent"] = g * b[4] + acc * b[5]
+    return out
+

@@ -9,7 +9,9 @@ the oracle's own gate loop in FP64.  Two entries are written:
   c128: that state, nullity tolerance 1e-7 (Algorithm 1);
   c64:  the same state rounded to complex64 and widened back to complex128 (the exact
         input of a complex64 run), nullity tolerance 1e-4 (the single-precision
-        reading of the tolerance).
+        reading of the tolerance); the same per-family steps of Algorithm 1, summed
+        over x with exact rounding, plus the totals over x of the sums that size the
+        single-precision rounding bounds.
 
 Each entry records S_2..4 = sum_x m_{alpha;x}, L = sum_x sum_z |F|^2 log2 |F|^2,
 P = sum_x p(x), nu_cnt, the largest gap over families, the derived M_1, M_2..4 and
@@ -57,9 +59,50 @@ def sha256(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
+def entry_c64(psi):
+    """The complex64 entry: Algorithm 1's per-family values of every x from the oracle, in
+    chunks (with the per-family sums that size the single-precision rounding bounds),
+    summed in x order with exact rounding (math.fsum)."""
+    n, d = N, 1 << N
+    eps = 1e-4
+    t0 = time.time()
+    psi128 = psi.astype(np.complex128)
+    cols = {k: [] for k in ("p", "ent", "m", "nu", "gap", "bsum")}
+    chunk = 1 << 14
+    for x0 in range(0, d, chunk):
+        r = oracle.eval_x_with_bound_sums(psi128, np.arange(x0, x0 + chunk, dtype=np.uint64), eps=eps, max_alpha=4)
+        for k in cols:
+            cols[k].append(r[k])
+        print("  c64 families %d / %d  %.0f s" % (x0 + chunk, d, time.time() - t0), flush=True)
+    a = {k: np.concatenate(v) for k, v in cols.items()}
+    S = [math.fsum(a["m"][:, k]) for k in range(3)]
+    L = math.fsum(a["ent"])
+    nu_cnt = int(np.sum(a["nu"]))
+    M, M1, nu = oracle.sre_from_sums(n, S, L, nu_cnt, (2, 3, 4))
+    return {
+        "state_sha256": sha256(psi),
+        "dtype": "c64",
+        "eps": eps,
+        "S": S,
+        "L": L,
+        "P": math.fsum(a["p"]),
+        "nu_cnt": nu_cnt,
+        "gap_max": float(np.max(a["gap"])),
+        "M": {str(k): M[k] for k in (2, 3, 4)},
+        "M1": M1,
+        "nullity": nu,
+        # sum over all x of the six per-family sums (oracle.eval_x_with_bound_sums) and of
+        # p and m_alpha: the first-order single-precision bounds are linear in them
+        "bound_sums": [math.fsum(a["bsum"][:, k]) for k in range(6)],
+        "oracle_seconds": round(time.time() - t0, 1),
+    }
+
+
 def entry(kind):
     psi = state_variant(config2_state(), kind)
-    eps = 1e-7 if kind == "c128" else 1e-4
+    if kind == "c64":
+        return entry_c64(psi)
+    eps = 1e-7
     t0 = time.time()
     r = oracle.alg1(psi.astype(np.complex128), eps=eps, max_alpha=4, per_x=True)
     px = r["per_x"]

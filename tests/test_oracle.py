@@ -106,6 +106,25 @@ def test_marginal_is_parseval_of_the_family_spectrum():
     assert abs(p_direct.sum() - 1) < 1e-13
 
 
+@pytest.mark.parametrize("n,seed", [(3, 71), (5, 72)])
+def test_bound_sums_match_bruteforce_spectrum(n, seed):
+    # the six per-family sums that size reduced-precision bounds, against the same sums
+    # over the brute-force values |c_P| of that family (the definition, no transform)
+    psi = synth.haar_state(n, seed)
+    c = np.abs(oracle.bruteforce(psi))
+    r = oracle.eval_x_with_bound_sums(psi, np.arange(1 << n))
+    for x in range(1 << n):
+        a = c[x]
+        lg = np.log2(a * a)
+        want = [a.sum(), (a ** 3).sum(), (a ** 5).sum(), (a ** 7).sum(),
+                np.abs(2 * a * lg + 2 * a / math.log(2)).sum(), np.abs(a * a * lg).sum()]
+        assert np.allclose(r["bsum"][x], want, rtol=1e-12, atol=1e-15), x
+    # and the outputs it shares with eval_x are the same numbers
+    r0 = oracle.eval_x(psi, np.arange(1 << n))
+    for k in ("p", "ent", "m", "nu", "gap"):
+        assert np.array_equal(r0[k], r[k]), k
+
+
 def test_psi_m_closed_forms():
     g = gold("paper_values.json")
     for n in (4, 6, 8, 10):
