@@ -283,10 +283,12 @@ typedef struct {
 } pw_mixed_result;
 PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out);
 
-/* Autotuning of families per launch for the bound state: times evaluation of a run
- * of consecutive families (4 x the workspace batch) at up to 6 candidate launch sizes
- * (the workspace batch and its halvings), keeps the fastest for this context and
- * records it for later binds of the same (device, n, dtype) in this process.
+/* Autotuning of families per launch for the bound state: times the evaluation of a
+ * list of uniformly drawn x (4 x the workspace batch, at most 4096; the sorted, grouped
+ * path that Monte Carlo steps and device lists take) at up to 6 candidate launch sizes
+ * (the workspace batch and its halvings, none below the first pass's tile-sharing group
+ * where the state has one), keeps the fastest for this context and records it for later
+ * binds of the same (device, n, dtype) in this process.
  * Optional outputs: candidates[i], us_per_family[i] (arrays of >= 6), n_candidates. */
 PW_API pw_status pw_autotune(pw_ctx ctx, int* best_batch, int* candidates, double* us_per_family, int* n_candidates);
 
@@ -307,6 +309,13 @@ typedef struct {
 } pw_state_ref;
 PW_API pw_status pw_eval_states(pw_ctx ctx, int nstates, const pw_state_ref* states, const int* state_idx,
                                 const uint64_t* xs, int64_t n_x, double eps, pw_xres* out);
+
+/* Test support for the error paths: every later HIP call of one class made by this
+ * context fails before it is issued (fault_class 1 = device or pinned allocation, 2 =
+ * kernel launch, 3 = copy; 0 = none, the default), so that a test can check that the
+ * failing call returns PW_ERR_HIP and leaves the context usable.  No GPU work is
+ * involved; the setting stays until changed. */
+PW_API pw_status pw_inject_fault(pw_ctx ctx, int fault_class);
 
 /* Graph replay for pw_mc (off by default): when enabled, one sampling step
  * (device-side draws whose counters come from a device counter, evaluation of their

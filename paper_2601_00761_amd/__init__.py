@@ -21,7 +21,7 @@ __all__ = [
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
     "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
@@ -117,6 +117,7 @@ def _load():
         "pw_mc": ([_vp, _int, _dbl, _int, _u64, _dbl, _u64, ctypes.POINTER(pw_result)], _int),
         "pw_set_moments": ([_vp, _int], _int),
         "pw_set_graphs": ([_vp, _int], _int),
+        "pw_inject_fault": ([_vp, _int], _int),
         "pw_autotune": ([_vp, ctypes.POINTER(_int), _vp, _vp, ctypes.POINTER(_int)], _int),
         "pw_eval_states": ([_vp, _int, _vp, _vp, _vp, _i64, _dbl, _vp], _int),
         "pw_mixed": ([_vp, _int, _dbl, ctypes.POINTER(pw_mixed_result)], _int),
@@ -304,6 +305,15 @@ def pw_eval_states(ctx, states, state_idx, xs, eps):
     _check(_L.pw_eval_states(ctx, len(states), arr, idx.ctypes.data, xs.ctypes.data, len(xs), float(eps),
                              out.ctypes.data))
     return out
+
+
+FAULT_CLASSES = {None: 0, "alloc": 1, "launch": 2, "copy": 3}
+
+
+def pw_inject_fault(ctx, kind):
+    """Make this context's HIP calls of one class ("alloc", "launch", "copy") fail before
+    they are issued; None clears it (tests of the error paths)."""
+    _check(_L.pw_inject_fault(ctx, FAULT_CLASSES[kind]))
 
 
 def pw_set_graphs(ctx, enable):

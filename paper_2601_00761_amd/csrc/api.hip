@@ -34,13 +34,6 @@ pw_status fail(pw_status s, const char* fmt, ...) {
     return s;
 }
 
-// Host-side fault injection for tests of the error paths: PW_FAULT=alloc|launch|copy
-// makes the named class of HIP call fail before it is issued.
-bool fault(const char* what) {
-    const char* f = getenv("PW_FAULT");
-    return f && strcmp(f, what) == 0;
-}
-
 #define PW_HIP(call)                                                                          \
     do {                                                                                      \
         hipError_t e_ = (call);                                                               \
@@ -198,9 +191,16 @@ struct pw_ctx_s {
     hipStream_t gstream = nullptr;  // non-blocking capture stream (default priority)
     hipEvent_t gfork = nullptr, gjoin = nullptr;
     bool capturing = false;
+    // error-path testing (pw_inject_fault): the class of HIP call made to fail
+    int fault_class = 0;
 };
 
 namespace {
+
+// Forced failure of one class of HIP call (1 allocation, 2 kernel launch, 3 copy) before
+// it is issued, set by pw_inject_fault for tests of the error paths.
+enum { FAULT_NONE = 0, FAULT_ALLOC = 1, FAULT_LAUNCH = 2, FAULT_COPY = 3 };
+inline bool fault(pw_ctx c, int cls) { return c->fault_class == cls; }
 
 hipEvent_t take_event(pw_ctx c) {
     if (!c->pool.empty()) {
@@ -287,7 +287,7 @@ pw_status prepare_workspace(pw_ctx c, int n, pw_dtype dt) {
                 c->ws = nullptr;
                 c->ws_bytes = 0;
             }
-            if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+            if (fault(c, FAULT_ALLOC)) return fail(PW_ERR_HIP, "hipMalloc: injected failure");
             void* p = nullptr;
             PW_HIP(hipMalloc(&p, need));
             c->ws = (char*)p;
@@ -309,7 +309,7 @@ pw_status run_norm(pw_ctx c, double* out) {
     double* res = part + np;
     unsigned* bad = reinterpret_cast<unsigned*>(part + np + 1);
     PW_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned), c->stream));
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     PW_HIP(norm2(c->dtype == PW_C128, c->psi, c->n, part, np, res, bad, c->stream));
     double h[2];
     PW_HIP(hipMemcpyAsync(h, res, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -348,7 +348,7 @@ pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, 
 
 pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
                          hipStream_t st) {
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     if (!d_xs || first_pass_group(c->P, c->dtype == PW_C128, c->run_batch) < 2)
         return eval_list_on(c, d_xs, x0, nx, eps, d_out, st);
     // tile-sharing groups: the list is evaluated in top-bit order, so that the families
@@ -375,7 +375,7 @@ pw_status eval_host(pw_ctx c, const uint64_t* xs, int64_t nx, double eps, Family
     FamilyRes* dr = at<FamilyRes>(c, c->L.xres);
     for (int64_t i = 0; i < nx; i += c->L.xcap) {
         const int nb = (int)((nx - i) < c->L.xcap ? (nx - i) : c->L.xcap);
-        if (fault("copy")) return fail(PW_ERR_HIP, "hipMemcpy: injected failure (PW_FAULT=copy)");
+        if (fault(c, FAULT_COPY)) return fail(PW_ERR_HIP, "hipMemcpy: injected failure");
         PW_HIP(hipMemcpyAsync(dx, xs + i, nb * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
         pw_status s = eval_device(c, dx, 0, nb, eps, dr);
         if (s != PW_OK) return s;
@@ -562,7 +562,7 @@ pw_status pw_state_upload(pw_ctx c, int n, pw_dtype dt, const void* host_psi, vo
     if (!host_psi || !dev_dst) return fail(PW_ERR_ARG, "null pointer");
     if (dt != PW_C128 && dt != PW_C64) return fail(PW_ERR_ARG, "unknown dtype %d", (int)dt);
     if (n < 1 || n > MAX_QUBITS) return fail(PW_ERR_RANGE, "n=%d outside [1, %d]", n, MAX_QUBITS);
-    if (fault("copy")) return fail(PW_ERR_HIP, "hipMemcpy: injected failure (PW_FAULT=copy)");
+    if (fault(c, FAULT_COPY)) return fail(PW_ERR_HIP, "hipMemcpy: injected failure");
     PW_HIP(hipMemcpyAsync(dev_dst, host_psi, ((size_t)1 << n) * esize(dt), hipMemcpyHostToDevice, c->stream));
     return pw_state_bind(c, n, dt, dev_dst, norm2_out);
 }
@@ -583,7 +583,7 @@ pw_status pw_apply_gates(pw_ctx c, int ng, const int* kinds, const int* qubits, 
             return fail(PW_ERR_ARG, "gate %d: unknown kind %d", g, kinds[g]);
         }
     }
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     const bool dbl = c->dtype == PW_C128;
     for (int g = 0; g < ng; ++g) {
         if (kinds[g] == 2) PW_HIP(apply_gate2(dbl, c->psi, c->n, qubits[2 * g], qubits[2 * g + 1], mats + 32 * g, c->stream));
@@ -623,7 +623,7 @@ pw_status pw_precondition(pw_ctx c, int n_layers, uint64_t seed) {
     if (s != PW_OK) return s;
     if (c->n < 2) return fail(PW_ERR_RANGE, "preconditioning needs n >= 2");
     if (n_layers < 0) return fail(PW_ERR_ARG, "negative layer count");
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     std::vector<int> q, idx, ls;
     brickwall_clifford(c->n, n_layers, seed, q, idx, &ls);
     ls.push_back((int)idx.size());
@@ -722,7 +722,7 @@ pw_status pw_family_values(pw_ctx c, uint64_t x, double* cvals) {
     void* G = c->ws + c->L.work;
     double* cv = reinterpret_cast<double*>(c->ws + c->L.work + align256(((size_t)1 << (c->n - 1)) * esize(c->dtype)));
     Plan P = make_plan(c->n, dbl);
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     PW_HIP(transform_one(P, dbl, c->psi, x, G, c->stream));
     PW_HIP(signed_values(P, dbl, G, x, cv, c->stream));
     PW_HIP(hipMemcpyAsync(cvals, cv, ((size_t)1 << c->n) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -737,7 +737,7 @@ pw_status pw_sample_x(pw_ctx c, pw_sampler sampler, uint64_t seed, uint64_t offs
     if (n > 0 && !xs_out) return fail(PW_ERR_ARG, "null output");
     if (sampler != PW_SAMPLER_UNIFORM_NZ && sampler != PW_SAMPLER_MARGINAL_NZ) return fail(PW_ERR_ARG, "unknown sampler");
     if (c->n < 1) return fail(PW_ERR_RANGE, "need n >= 1");
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     uint64_t* dx = at<uint64_t>(c, c->L.xs);
     if (sampler == PW_SAMPLER_MARGINAL_NZ && !c->cdf_valid) {
         PW_HIP(build_cdf(c->dtype == PW_C128, c->psi, c->n, at<double>(c, c->L.cdf), at<double>(c, c->L.cdfblk), c->stream));
@@ -759,7 +759,7 @@ pw_status pw_exact(pw_ctx c, double eps, pw_result* out) {
     if (!out) return fail(PW_ERR_ARG, "null output");
     if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
     if (c->n > EXACT_MAX_QUBITS) return fail(PW_ERR_RANGE, "exact enumeration limited to n <= %d", EXACT_MAX_QUBITS);
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     const uint64_t d = 1ull << c->n;
     SweepSums* sw = at<SweepSums>(c, c->L.sweep);
     SweepSums* fin = sw + SWEEP_SLOTS;
@@ -994,7 +994,7 @@ pw_status pw_made_init(pw_ctx c, int n, int hidden, const double* params) {
     const size_t oO = carve(outb), odO = carve(outb);
     const size_t olq = carve((size_t)M.maxB * 8), oxs = carve((size_t)M.maxB * 8), ow = carve((size_t)M.maxB * 4),
                  operm = carve((size_t)M.maxB * 4);
-    if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+    if (fault(c, FAULT_ALLOC)) return fail(PW_ERR_HIP, "hipMalloc: injected failure");
     PW_HIP(hipMalloc(&M.block, off));
     char* b = (char*)M.block;
     M.P = (float*)(b + oP);
@@ -1283,11 +1283,11 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
             c->rho = nullptr;
             c->rho_bytes = 0;
         }
-        if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+        if (fault(c, FAULT_ALLOC)) return fail(PW_ERR_HIP, "hipMalloc: injected failure");
         PW_HIP(hipMalloc(&c->rho, bytes));
         c->rho_bytes = bytes;
     }
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
     PW_HIP(reduced_density(dbl, c->psi, c->n, n_a, c->rho, c->stream, timer_of(c)));
     FamilyRes* fam = at<FamilyRes>(c, c->L.fam);
     void* work = (char*)c->rho + rho_b;
@@ -1320,13 +1320,24 @@ pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per
     pw_status s = check_state(c);
     if (s != PW_OK) return s;
     if (!best_batch) return fail(PW_ERR_ARG, "null output");
-    if (fault("launch")) return fail(PW_ERR_HIP, "kernel launch: injected failure (PW_FAULT=launch)");
-    // candidate families per launch: powers of two up to the workspace batch
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
+    // candidate families per launch: powers of two up to the workspace batch, not below
+    // the tile-sharing group of the first pass where the state has one (a smaller launch
+    // would switch the groups off)
+    const bool dbl = c->dtype == PW_C128;
+    const int bmin = first_pass_group(c->P, dbl, 4);
     std::vector<int> cand;
-    for (int b = c->batch; b >= 1 && (int)cand.size() < 6; b /= 2) cand.push_back(b);
+    for (int b = c->batch; b >= bmin && (int)cand.size() < 6; b /= 2) cand.push_back(b);
+    if (cand.empty()) cand.push_back(c->batch);
+    // the timed work is what Monte Carlo steps and device lists run: a list of uniformly
+    // drawn x (Philox stream keyed 0x7475) through the sorted, grouped evaluation
     const uint64_t d = 1ull << c->n;
-    const int64_t total = (int64_t)((uint64_t)(4 * c->batch) < d ? (uint64_t)(4 * c->batch) : d);
-    const uint64_t x0 = d > (uint64_t)(2 * total) ? (d >> 1) : 0;   // a run of consecutive families
+    int64_t total = 4 * (int64_t)c->batch;
+    if (total > c->L.xcap) total = c->L.xcap;
+    if ((uint64_t)total > d - 1) total = (int64_t)(d - 1);
+    if (total < 1) total = 1;
+    uint64_t* dx = at<uint64_t>(c, c->L.xs);
+    PW_HIP(sample_uniform(c->n, 0x7475, 0, total, dx, c->stream));
     hipEvent_t e0, e1;
     PW_HIP(hipEventCreate(&e0));
     PW_HIP(hipEventCreate(&e1));
@@ -1342,7 +1353,7 @@ pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {   // first repetition warms up
             PW_HIP(hipEventRecord(e0, c->stream));
-            s = eval_device(c, nullptr, x0, total, 1e-4, fam);
+            s = eval_device(c, dx, 0, total, 1e-4, fam);
             if (s != PW_OK) break;
             PW_HIP(hipEventRecord(e1, c->stream));
             PW_HIP(hipEventSynchronize(e1));
@@ -1450,7 +1461,7 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
                 c->ws = nullptr;
                 c->ws_bytes = 0;
             }
-            if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+            if (fault(c, FAULT_ALLOC)) return fail(PW_ERR_HIP, "hipMalloc: injected failure");
             void* p = nullptr;
             PW_HIP(hipMalloc(&p, need));
             c->ws = (char*)p;
@@ -1464,7 +1475,7 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
                 c->pin = nullptr;
                 c->pin_bytes = 0;
             }
-            if (fault("alloc")) return fail(PW_ERR_HIP, "hipHostMalloc: injected failure (PW_FAULT=alloc)");
+            if (fault(c, FAULT_ALLOC)) return fail(PW_ERR_HIP, "hipHostMalloc: injected failure");
             PW_HIP(hipHostMalloc(&c->pin, pin_need, hipHostMallocDefault));
             c->pin_bytes = pin_need;
         }
@@ -1475,7 +1486,7 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
                 c->nrm = nullptr;
                 c->nrm_bytes = 0;
             }
-            if (fault("alloc")) return fail(PW_ERR_HIP, "hipMalloc: injected failure (PW_FAULT=alloc)");
+            if (fault(c, FAULT_ALLOC)) return fail(PW_ERR_HIP, "hipMalloc: injected failure");
             PW_HIP(hipMalloc(&c->nrm, nrm_need));
             c->nrm_bytes = nrm_need;
         }
@@ -1557,6 +1568,14 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
     s = restore(s);
     if (s != PW_OK) return s;
     for (int64_t j = 0; j < n_x; ++j) memcpy(out + order[(size_t)j], hres + j, sizeof(FamilyRes));
+    return PW_OK;
+}
+
+pw_status pw_inject_fault(pw_ctx c, int cls) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (cls < FAULT_NONE || cls > FAULT_COPY) return fail(PW_ERR_ARG, "fault class %d outside [0, 3]", cls);
+    c->fault_class = cls;
     return PW_OK;
 }
 
