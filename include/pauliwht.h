@@ -344,6 +344,21 @@ PW_API pw_status pw_timing_enable(pw_ctx ctx, int every);
 PW_API pw_status pw_timing_read(pw_ctx ctx, int kclass, uint64_t* samples, double* total_ms, uint64_t* families);
 PW_API pw_status pw_timing_reset(pw_ctx ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pw_eval_x_device without a context or
+ * a workspace.  The families of the device list d_xs[0..n_x) (each x taken modulo 2^n)
+ * of the device state dev_psi (2^n amplitudes of dtype, 256-byte aligned, borrowed,
+ * not norm-checked) are written to the device array d_out in list order, moments up to
+ * alpha = 4; the work is enqueued on hip_stream (a hipStream_t of the calling thread's
+ * current device; NULL = default stream) without synchronising.  The kernels are those of
+ * pw_eval_x_device, with results bitwise equal to it.  Their scratch is a static device
+ * array of 128 MiB per GPU (held until the process ends): complex64 states up to n = 24,
+ * complex128 up to n = 23; larger states return PW_ERR_WORKSPACE.  No device or host
+ * memory is allocated.  Calls that overlap on one GPU share that scratch and race:
+ * serialise them (one stream, or events).  Errors as elsewhere (pw_last_error). */
+PW_API pw_status pw_eval_x_noalloc(void* hip_stream, int n_qubits, pw_dtype dtype, const void* dev_psi,
+                                   const uint64_t* d_xs, int64_t n_x, double eps, pw_xres* d_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ __all__ = [
     "PWError", "PW_C128", "PW_C64", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
-    "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_family_values",
+    "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_eval_x_noalloc", "pw_family_values",
     "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
@@ -111,6 +111,7 @@ def _load():
         "pw_clifford2_table": ([ctypes.POINTER(_int), _vp], _int),
         "pw_eval_x": ([_vp, _vp, _i64, _dbl, _vp], _int),
         "pw_eval_x_device": ([_vp, _vp, _i64, _dbl, _vp], _int),
+        "pw_eval_x_noalloc": ([_vp, _int, _int, _vp, _vp, _i64, _dbl, _vp], _int),
         "pw_family_values": ([_vp, _u64, _vp], _int),
         "pw_sample_x": ([_vp, _int, _u64, _u64, _i64, _vp], _int),
         "pw_exact": ([_vp, _dbl, ctypes.POINTER(pw_result)], _int),
@@ -250,6 +251,12 @@ def pw_eval_x(ctx, xs, eps):
 
 def pw_eval_x_device(ctx, d_xs, n_x, eps, d_out):
     _check(_L.pw_eval_x_device(ctx, _ptr(d_xs), int(n_x), float(eps), _ptr(d_out)))
+
+
+def pw_eval_x_noalloc(stream, n, dtype, dev_psi, d_xs, n_x, eps, d_out):
+    """The families of a device list without a context or workspace (static scratch)."""
+    _check(_L.pw_eval_x_noalloc(_stream_handle(stream), int(n), int(dtype), _ptr(dev_psi), _ptr(d_xs), int(n_x),
+                                float(eps), _ptr(d_out)))
 
 
 def pw_family_values(ctx, x, n):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["fwht.hip", "state.hip", "sample.hip", "made.hip", "clifford.hip", "api.hip"]
+SOURCES = ["fwht.hip", "state.hip", "sample.hip", "made.hip", "clifford.hip", "api.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "libpauliwht.so")
 ARCH = os.environ.get("PW_OFFLOAD_ARCH", "gfx950")
 

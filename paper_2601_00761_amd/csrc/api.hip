@@ -23,6 +23,13 @@ namespace {
 
 thread_local std::string g_err;
 
+}  // namespace
+
+// The calling thread's message buffer, shared with the entry point of noalloc.hip.
+std::string& pw::last_error_ref() { return g_err; }
+
+namespace {
+
 pw_status fail(pw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 pw_status fail(pw_status s, const char* fmt, ...) {
     char buf[512];

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <string>
 #include <vector>
 
 namespace pw {
@@ -57,6 +58,9 @@ struct Plan {
 };
 
 Plan make_plan(int n, bool dbl);
+
+// Message buffer behind pw_last_error (thread-local).
+std::string& last_error_ref();
 
 // Families per group of the first pass that share their state tiles (1, 2 or 4; more
 // than 1 only for multi-pass plans of states of 16 MiB and more, and at most nb).  The
