@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
-"""Throughput of the FWHT Pauli-string path on one MI355X.
+"""Throughput of the FWHT Pauli-string path on one MI355X, and M_2 wall time at a fixed
+standard error.
 
-Workload: an N = 20 T-doped random Clifford state (|0...0> followed by uniformly
-random two-qubit Cliffords in brick-wall order with eta = 20 Cliffords per T gate and
-N_T = 20 T gates on random qubits), and exact enumeration of all 4^20 Pauli
-strings: every X-bitstring x is evaluated (product, transform over all 2^20 z,
-moments, Shannon term, nullity count), then S_alpha, M_1, M_alpha and the nullity
-are formed.  One step is one full enumeration (2^40 Pauli strings).  The main
-leg runs the transform in FP32 on a complex64 state; a second leg times the FP64
-path on the complex128 state.
+Headline workload: an N = 28 T-doped random Clifford state in complex64 (2 GiB;
+|0...0> followed by uniformly random two-qubit Cliffords in brick-wall order, one T on a
+random qubit after every eta = 16 of them, N_T = 2N = 56), Clifford-preconditioned by the
+library (2N = 56 random brick-wall Clifford layers, timed), then Monte Carlo over
+X-bitstrings: x = 0 plus x drawn from the exact x-marginal on the device, evaluated in
+launches of 64 families (product, transform over all 2^28 z, moments, Shannon term,
+nullity count), and the estimate of S_2, M_2, M_1 with its standard error.  One step is
+one Monte Carlo estimate over 2048 drawn families (plus x = 0); value = Pauli strings
+evaluated per second (families x 2^28) over the timed steps, the state resident in HBM.
+The roofline is HBM: one read of the 2 GiB state per family is the algorithmic traffic.
 
-Prints one JSON line.  The input lives in HBM before the timed region; the state
-is prepared on the GPU by the library's gate kernels (input generation, untimed).
+Second part of the metric: M_2 to a standard error of 1e-3 on the same state, the
+sampler chosen from a pilot (pw_mc_auto), capped by a wall-time budget.
+
+Extra legs in the same JSON line: the N = 20 exact enumeration of all 4^20 Pauli
+strings (complex64 and complex128), the N = 30 learned-proposal comparison, and the
+FP64 CPU oracle on a bounded sample of the headline families.
+
+Prints one JSON line.  State preparation runs on the GPU through the library's gate
+kernels (input generation, untimed).
 """
 import argparse
 import hashlib
@@ -28,28 +38,10 @@ N_QUBITS = 20
 ETA = 20
 N_T = 20
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU peak in lane-operations/s: the published 157.3 TFLOP/s FP32 vector rate counts
-# an FMA as two operations, i.e. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6e12 VALU
-# lane-operations/s (a dependent-free add chain with vector operands reaches 74e12 here,
-# with packed FP32 disabled); an add, a multiply or an FMA counts as one operation.
-VALU_PEAK_GOPS = 256 * 4 * 32 * 2.4
 KCLASS = {0: "k_fused", 1: "k_first", 2: "k_column(mid)", 3: "k_column(last)"}
-# kernel-name prefixes as rocprofv3 reports them (first pass: shared-tile variant for sweeps)
-KNAME = {0: "k_fused", 1: "k_first_shared", 2: "k_column", 3: "k_column"}
-
-
-def algorithmic_ops_per_point(kclass, n, bits_in_pass):
-    """Minimal VALU operations per point of the half-size spectrum for one kernel class:
-    product conj(a) c = 4 (2 mul + 2 fma); each radix-2 stage 2 (re and im add/sub);
-    reductions per magnitude 7 (square, sum, fourth power, sum, log2, Shannon fma,
-    running max for the nullity test), two magnitudes per point."""
-    if kclass == 0:
-        return 4 + 2 * (n - 1) + 14
-    if kclass == 1:
-        return 4 + 2 * 12
-    if kclass == 2:
-        return 2 * bits_in_pass
-    return 2 * bits_in_pass + 14
+# counter summaries per kernel of the N = 28 Monte Carlo path (rocprofv3 kernel-name prefixes)
+KNAME_MC = {0: "k_fused", 1: "k_first", 2: "k_column", 3: "k_column"}
+TRAFFIC_N28 = "pmc_traffic_c64_n28_mc.json"
 
 
 def kernel_source_hash():
@@ -75,23 +67,6 @@ def load_traffic(kernel, summary="pmc_traffic_c64_n20.json", field="hbm_bytes_pe
     if not k:
         return None
     return k.get(field)
-
-
-def fill_ceiling(torch, nbytes=256 << 20, reps=20):
-    """GB/s of a plain fill of nbytes (torch fill_, timed with events on torch's stream):
-    the write ceiling of the memory fabric for one launch's worth of half spectra."""
-    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
-    for _ in range(3):
-        buf.fill_(1.0)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for i in range(reps):
-        buf.fill_(float(i))
-    b.record()
-    b.synchronize()
-    gbps = nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
-    del buf
-    return gbps
 
 
 def copy_ceiling(torch, nbytes=1 << 30, reps=10):
@@ -120,29 +95,6 @@ def prepare_state(pw, torch, n, seed):
     psi0 = np.zeros(1 << n, dtype=np.complex128)
     psi0[0] = 1.0
     return psi0, (kinds, qubits, mats)
-
-
-def cpu_baseline(psi128, budget_s):
-    """The FP64 oracle (Algorithm 1 per family) on a bounded sample of the same
-    enumeration: families x = 0, 1, 2, ... until budget_s seconds of host time."""
-    import numpy as np
-    import oracle
-    n = int(round(math.log2(len(psi128))))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    done = 0
-    t0 = time.perf_counter()
-    chunk = 4
-    while True:
-        xs = np.arange(done, done + chunk, dtype=np.uint64)
-        oracle.eval_x(psi128, xs, eps=1e-7, max_alpha=4)
-        done += chunk
-        el = time.perf_counter() - t0
-        if el >= budget_s or done >= (1 << n):
-            break
-    el = time.perf_counter() - t0
-    return {"value": done * float(1 << n) / el, "unit": "Pauli strings/s", "cores": threads, "kind": "oracle",
-            "sample": "families x = 0..%d of the N=%d enumeration (%d of %d families, %.1f s, FP64 Algorithm 1 "
-                      "with OpenMP inside each transform stage)" % (done - 1, n, done, 1 << n, el)}
 
 
 MC_N = 28
@@ -473,76 +425,197 @@ def learned_leg(pw, torch, stream, kind, draws, pilot):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--steps-c128", type=int, default=2)
-    ap.add_argument("--timing-every", type=int, default=16, help="time every k-th launch of each kernel class")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mc-leg", action="store_true", help="skip the N=28 Monte Carlo leg")
-    ap.add_argument("--mc-eta", type=int, nargs="+", default=[4],
-                    help="scrambling ratios of the N=28 Monte Carlo leg (the workload lists 1, 4 and 16)")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="families per launch (0: the library default for the state size)")
-    ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=None,
-                    help="also run the N=30 learned-vs-plain proposal comparison (minutes; off by default)")
-    ap.add_argument("--haar-leg", action="store_true",
-                    help="add the Haar brick-wall leg (N=24, d_H = 1, 2, 4; r_2 before / after preconditioning)")
-    ap.add_argument("--haar-draws", type=int, default=2048, help="draws per estimate in the Haar brick-wall leg")
-    ap.add_argument("--mixed-leg", action="store_true",
-                    help="add the mixed-state leg (N=24, n_a = 14 / 13, complex64 / complex128)")
-    ap.add_argument("--multistate-leg", action="store_true",
-                    help="also run the 64-state uneven-N batch (minute-scale; off by default)")
-    ap.add_argument("--learned-draws", type=int, default=2048)
-    ap.add_argument("--learned-pilot", type=int, default=4096)
-    ap.add_argument("--max-alpha", type=int, default=2, choices=(2, 4),
-                    help="moments computed per family (the workload asks for M_1, M_2 and the nullity)")
-    args = ap.parse_args()
+HEAD_N = 28
+HEAD_BATCH = 64           # families per launch (a lent workspace of 64 families)
+HEAD_FAMILIES = 2048      # drawn families per step
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path (the method would shard over x). "
-              "Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
 
+def host_cpu_record():
+    """Host CPU of this machine: model, logical CPUs, the CPUs this process may use."""
+    rec = {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                rec["lscpu_" + k.strip().replace(" ", "_").replace("(", "").replace(")", "")] = v.strip()
+    except Exception as e:   # lscpu missing: the counts above stand
+        rec["lscpu_error"] = str(e)
+    return rec
+
+
+def headline_state(pw, torch, stream, eta):
+    """The N = 28 T-doped Clifford state in complex64 on the device (library gate kernels),
+    bound to a context with a lent 64-family workspace; then the library's Clifford
+    preconditioning (2N layers), timed."""
     import numpy as np
-    import torch
-    import paper_2601_00761_amd as pw
     import synth
+    n = HEAD_N
+    seed = synth.SEED_BASE + 3 + 100 * eta
+    kinds, qubits, mats = synth.gates_to_arrays(synth.tdoped_stream(n, eta, 2 * n, seed))
+    psi0 = np.zeros(1 << n, dtype=np.complex64)
+    psi0[0] = 1.0
+    ctx = pw.Context(0, stream)
+    pw.pw_set_moments(ctx.h, 2)
+    ctx.upload(psi0, pw.PW_C64, x_batch=HEAD_BATCH)
+    del psi0
+    ctx.apply_gates(kinds, qubits, mats)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.precondition(2 * n, seed + 1)
+    torch.cuda.synchronize()
+    return ctx, seed, time.perf_counter() - t0
 
+
+def headline_steps(pw, torch, ctx, seed, steps, warmup):
+    """Monte Carlo steps on the headline state: each step draws HEAD_FAMILIES x from the exact
+    marginal (device sampler) and evaluates them with x = 0, in launches of 64 families,
+    eagerly, with HIP events attached to every launch of the timed steps (the kernels'
+    own dispatch intervals on the context stream)."""
+    pw.pw_set_graphs(ctx.h, 0)
+    for w in range(warmup):
+        ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, HEAD_BATCH, HEAD_FAMILIES + 1, 0.0, seed + 1000 + w)
+    pw.pw_timing_enable(ctx.h, 1)
+    pw.pw_timing_reset(ctx.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fams = 0
+    last = None
+    for k in range(steps):
+        last = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, HEAD_BATCH, HEAD_FAMILIES + 1, 0.0, seed + 2000 + k)
+        fams += last["n_samples"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {}
+    for kc in range(4):
+        cnt, ms, fam = pw.pw_timing_read(ctx.h, kc)
+        if cnt:
+            kt[kc] = dict(launches=cnt, avg_ms=ms / cnt, families_per_launch=fam / cnt)
+    pw.pw_timing_enable(ctx.h, 0)
+    return el, fams, last, kt
+
+
+def headline_roofline(torch, kt):
+    """HBM roofline of the dominant kernel (largest time per family): algorithmic bytes =
+    one read of the 2 GiB state per family x the families of one launch, over the kernel's
+    average launch duration (HIP events over the timed steps); counter traffic per launch
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the same kernels."""
+    n = HEAD_N
+    alg = float(1 << n) * 8.0
+    dom = max(kt, key=lambda k: kt[k]["avg_ms"] / kt[k]["families_per_launch"])
+    d = kt[dom]
+    achieved = alg * d["families_per_launch"] / (d["avg_ms"] * 1e-3) / 1e9
+    t_fam = load_traffic(KNAME_MC[dom], TRAFFIC_N28, "hbm_bytes_per_family")
+    traffic = t_fam * d["families_per_launch"] if t_fam is not None else None
+    path_us = sum(v["avg_ms"] * 1e3 / v["families_per_launch"] for v in kt.values())
+    path_gbps = alg / (path_us * 1e-6) / 1e9
+    t_first = load_traffic("k_first", TRAFFIC_N28, "hbm_bytes_per_family")
+    t_col = load_traffic("k_column", TRAFFIC_N28, "hbm_bytes_per_family")
+    path_traffic = t_first + t_col if t_first is not None and t_col is not None else None
+    copy = copy_ceiling(torch)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": KCLASS[dom], "kernel_avg_us": round(d["avg_ms"] * 1e3, 2),
+            "families_per_launch": d["families_per_launch"], "algorithmic_bytes_per_family": alg,
+            "per_class_avg_us": {KCLASS[k]: round(v["avg_ms"] * 1e3, 2) for k, v in kt.items()},
+            "path": {"us_per_family": round(path_us, 2), "algorithmic_GBps": round(path_gbps, 1),
+                     "frac": round(path_gbps / HBM_PEAK_GBS, 4),
+                     "traffic_bytes_per_family": path_traffic,
+                     "traffic_GBps": round(path_traffic / (path_us * 1e-6) / 1e9, 1) if path_traffic else None,
+                     "note": "both passes per family: one read of psi over the summed kernel time"},
+            "copy_ceiling": {"GBps": round(copy, 1),
+                             "path_traffic_frac": round(path_traffic / (path_us * 1e-6) / 1e9 / copy, 4)
+                             if path_traffic else None,
+                             "note": "device-to-device copy of 1 GiB (torch copy_), read + write bytes over time"}}
+    if traffic is not None:
+        roof["traffic_GBps"] = round(traffic / (d["avg_ms"] * 1e-3) / 1e9, 1)
+    return roof
+
+
+def headline_cpu_baseline(pw, ctx, seed, budget_s):
+    """The FP64 oracle (Algorithm 1 per family, OpenMP inside each transform stage) on a
+    bounded sample of the headline work: the same state bytes (copied back, widened to
+    complex128) and the families x = 0 and the first exact-marginal draws of the first
+    timed step, one at a time until budget_s seconds."""
+    import numpy as np
+    import oracle
+    n = HEAD_N
+    psi = ctx.psi.cpu().numpy().astype(np.complex128)
+    draws = ctx.sample_x(pw.PW_SAMPLER_MARGINAL_NZ, seed + 2000, 0, 64)
+    xs = np.concatenate([[0], draws]).astype(np.uint64)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(xs):
+        oracle.eval_x(psi, xs[done:done + 1], eps=1e-4, max_alpha=2)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    del psi
+    return {"value": done * float(1 << n) / el, "unit": "Pauli strings/s", "cores": threads, "kind": "oracle",
+            "sample": "families x = 0 and the first %d exact-marginal draws of the first timed step of the N=%d "
+                      "headline (same state bytes, widened to complex128), %.1f s of FP64 Algorithm 1 with OpenMP "
+                      "inside each transform stage" % (done - 1, n, el),
+            "host": host_cpu_record()}
+
+
+def sigma_leg(pw, torch, ctx, seed, budget_s, per_family_s, precondition_s):
+    """M_2 to a standard error of 1e-3 on the headline state: pw_mc_auto (one 2048-draw
+    exact-marginal pilot estimates the spread of both samplers; the smaller wins), sampling
+    steps replayed as HIP graphs, at most as many families as budget_s allows at the measured
+    cost per family."""
+    cap = max(4096, int(budget_s / per_family_s))
+    pw.pw_set_graphs(ctx.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, chosen, r2 = pw.pw_mc_auto(ctx.h, 1e-4, HEAD_BATCH, cap + 1, MC_TARGET_SE, seed + 3, 2048)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pw.pw_set_graphs(ctx.h, 0)
+    se = res["M_se"][0]
+    return {"workload": "M_2 of the headline state (N=%d, complex64, preconditioned) to std-err %g; exact-marginal pilot of 2048 "
+                        "draws, the sampler with the smaller spread then runs to the target or the family cap"
+                        % (HEAD_N, MC_TARGET_SE),
+            "sampler": "uniform" if chosen == pw.PW_SAMPLER_UNIFORM_NZ else "exact marginal",
+            "pilot": {"r2_uniform": r2[0], "r2_marginal": r2[1],
+                      "note": "both spreads estimated from one 2048-draw exact-marginal pilot"},
+            "M2": res["M"][0], "M2_se": se, "M1": res["M1"], "M1_se": res["M1_se"], "r2": res["r"][0],
+            "n_samples": res["n_samples"], "family_cap": cap + 1, "target_reached": bool(se <= MC_TARGET_SE),
+            "families_for_se_target": res["n_samples"] * (se / MC_TARGET_SE) ** 2,
+            "wall_s": el + precondition_s, "sampling_s": el, "precondition_s": precondition_s,
+            "note": "wall_s = preconditioning + pilots + sampling to the target"}
+
+
+def sweep20_leg(pw, torch, stream, steps, warmup, steps_c128, timing_every, max_alpha):
+    """Exact enumeration of all 4^20 Pauli strings of the N = 20 T-doped Clifford state
+    (eta = 20, N_T = 20): complex64 (FP32 transform) and complex128 (FP64)."""
+    import synth
     n = N_QUBITS
     seed = synth.SEED_BASE + 2
     psi0, gates = prepare_state(pw, torch, n, seed)
-
-    stream = torch.cuda.current_stream(0)
-    # state preparation on the GPU in FP64, then a complex64 copy for the main leg
     prep = pw.Context(0, stream)
     prep.upload(psi0, pw.PW_C128)
     prep.apply_gates(*gates)
-    psi128_dev = prep.psi
-    psi64_dev = psi128_dev.to(torch.complex64)
+    psi128 = prep.psi
+    psi64 = psi128.to(torch.complex64)
     torch.cuda.synchronize()
+    strings = float(1 << n) ** 2
 
-    results = {}
-
-    def leg(dtype, psi_dev, steps, warmup, eps, timing):
+    def run(dtype, psi_dev, st, wu, eps, timing):
         ctx = pw.Context(0, stream)
-        pw.pw_set_moments(ctx.h, args.max_alpha)
-        if args.batch:
-            ctx.reserve(n, dtype, args.batch)
+        pw.pw_set_moments(ctx.h, max_alpha)
         ctx.bind(psi_dev, dtype)
-        for _ in range(warmup):
+        for _ in range(wu):
             ctx.exact(eps)
         if timing:
-            pw.pw_timing_enable(ctx.h, args.timing_every)
+            pw.pw_timing_enable(ctx.h, timing_every)
             pw.pw_timing_reset(ctx.h)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         last = None
-        for _ in range(steps):
+        for _ in range(st):
             last = ctx.exact(eps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
@@ -551,104 +624,121 @@ def main():
             for k in range(4):
                 cnt, ms, fam = pw.pw_timing_read(ctx.h, k)
                 if cnt:
-                    kt[k] = dict(samples=cnt, avg_ms=ms / cnt, families_per_launch=fam / cnt)
-            pw.pw_timing_enable(ctx.h, 0)
-        batch = ctx_batch = None
+                    kt[KCLASS[k]] = round(ms / cnt * 1e3, 2)
         ctx.close()
         return el, last, kt
 
-    el64, r64, kt64 = leg(pw.PW_C64, psi64_dev, args.steps, args.warmup, 1e-4, True)
-    strings = float(1 << n) ** 2
-    value = args.steps * strings / el64
+    el64, r64, kt64 = run(pw.PW_C64, psi64, steps, warmup, 1e-4, True)
+    out = {"workload": "exact enumeration of all 4^20 Pauli strings of an N=20 T-doped random Clifford state "
+                       "(eta=20, N_T=20, from |0..0>)",
+           "c64": {"pauli_strings_per_s": steps * strings / el64, "ms_per_step": 1e3 * el64 / steps, "steps": steps,
+                   "dtype": "f32", "M1": r64["M1"], "M2": r64["M"][0], "nullity": r64["nullity"], "P": r64["P"],
+                   "kernel_avg_us": kt64}}
+    if steps_c128 > 0:
+        el128, r128, _ = run(pw.PW_C128, psi128, steps_c128, 1, 1e-7, False)
+        out["c128"] = {"pauli_strings_per_s": steps_c128 * strings / el128, "ms_per_step": 1e3 * el128 / steps_c128,
+                       "steps": steps_c128, "dtype": "f64", "M1": r128["M1"], "M2": r128["M"][0],
+                       "nullity": r128["nullity"], "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0]}
+    prep.close()
+    return out
 
-    # dominant kernel = largest share of the sampled time per family.  The algorithmic
-    # bytes of the path are one read of the 8 MiB state per family (served from L2/MALL at
-    # N = 20), far below what the arithmetic needs, so the roof is VALU issue: achieved =
-    # algorithmic VALU operations per launch / duration.  The counter traffic of the same
-    # kernel (the half spectra it writes) is reported beside it as a rate.
-    dom = max(kt64, key=lambda k: kt64[k]["avg_ms"] / kt64[k]["families_per_launch"])
-    d = kt64[dom]
-    half_points = float(1 << (n - 1))
-    ops_pt = algorithmic_ops_per_point(dom, n, (n - 1) - 12)
-    alg_ops = d["families_per_launch"] * half_points * ops_pt
-    achieved = alg_ops / (d["avg_ms"] * 1e-3) / 1e9
-    path_us = sum(v["avg_ms"] * 1e3 / v["families_per_launch"] for v in kt64.values())
-    alg_bytes_family = float(1 << n) * 8.0       # one read of psi per family (complex64)
-    traffic = load_traffic(KNAME[dom])
-    roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
-                "frac": round(achieved / VALU_PEAK_GOPS, 4),
-                "traffic": traffic, "kernel": KCLASS[dom],
-                "kernel_avg_us": round(d["avg_ms"] * 1e3, 2), "families_per_launch": d["families_per_launch"],
-                "algorithmic_ops_per_point": ops_pt,
-                "algorithmic_ops_per_launch": alg_ops,
-                "per_class_avg_us": {KCLASS[k]: round(v["avg_ms"] * 1e3, 2) for k, v in kt64.items()},
-                "path_us_per_family": round(path_us, 4),
-                "hbm_equivalent": {"algorithmic_bytes_per_family": alg_bytes_family,
-                                   "GBps": round(alg_bytes_family / (path_us * 1e-6) / 1e9, 1),
-                                   "frac_of_hbm_peak": round(alg_bytes_family / (path_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                                                             4),
-                                   "note": "one read of psi per family over the whole path time (the state is served "
-                                           "from L2/MALL at N = 20, so this is an equivalent, not HBM traffic)"}}
-    if traffic is not None:
-        roofline["traffic_GBps"] = round(traffic / (d["avg_ms"] * 1e-3) / 1e9, 1)
-        roofline["traffic_note"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch (L2 <-> fabric: MALL or HBM) "
-                                    "over the HIP-event duration")
-    if traffic is not None and dom == 1:
-        # what bounds the first pass in practice: the fabric's write rate for the batch's
-        # half spectra, measured here by a plain fill of the same size
-        fill = fill_ceiling(torch, int(d["families_per_launch"] * half_points * 8))
-        roofline["fill_ceiling"] = {"GBps": round(fill, 1), "traffic_frac": round(roofline["traffic_GBps"] / fill, 4),
-                                    "note": "plain fill (torch fill_) of the bytes the launch writes, same GPU"}
 
-    el128 = r128 = None
-    if args.steps_c128 > 0:
-        el128, r128, _ = leg(pw.PW_C128, psi128_dev, args.steps_c128, 1, 1e-7, False)
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--eta", type=int, default=16, help="scrambling ratio of the headline state (workload: 1, 4, 16)")
+    ap.add_argument("--sigma-budget", type=float, default=240.0,
+                    help="wall seconds the M_2-to-1e-3 leg may spend sampling (0: skip it)")
+    ap.add_argument("--total-budget", type=float, default=540.0,
+                    help="the sigma leg is shortened so that the whole run stays within this many seconds")
+    ap.add_argument("--sweep-steps", type=int, default=2, help="timed N=20 exact sweeps in complex64 (0: skip)")
+    ap.add_argument("--steps-c128", type=int, default=1)
+    ap.add_argument("--timing-every", type=int, default=16, help="N=20 leg: time every k-th launch of each class")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-draws", type=int, default=1024)
+    ap.add_argument("--learned-pilot", type=int, default=2048)
+    ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=["tdoped"],
+                    help="N=30 learned-vs-plain proposal comparison (default: the T-doped state of the workload)")
+    ap.add_argument("--no-learned-leg", action="store_true")
+    ap.add_argument("--mc-eta", type=int, nargs="*", default=[],
+                    help="extra N=28 Monte Carlo legs (marginal sampler, 16384 families) at these eta")
+    ap.add_argument("--haar-leg", action="store_true",
+                    help="add the Haar brick-wall leg (N=24, d_H = 1, 2, 4; r_2 before / after preconditioning)")
+    ap.add_argument("--haar-draws", type=int, default=2048, help="draws per estimate in the Haar brick-wall leg")
+    ap.add_argument("--mixed-leg", action="store_true",
+                    help="add the mixed-state leg (N=24, n_a = 14 / 13, complex64 / complex128)")
+    ap.add_argument("--multistate-leg", action="store_true",
+                    help="also run the 64-state uneven-N batch (minute-scale; off by default)")
+    ap.add_argument("--max-alpha", type=int, default=2, choices=(2, 4),
+                    help="N=20 leg: moments computed per family (the workload asks for M_1, M_2 and the nullity)")
+    args = ap.parse_args()
 
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the method would shard over x). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    t_start = time.perf_counter()
+    import torch
+    import paper_2601_00761_amd as pw
+
+    stream = torch.cuda.current_stream(0)
+    ctx, seed, pre_s = headline_state(pw, torch, stream, args.eta)
+    el, fams, last, kt = headline_steps(pw, torch, ctx, seed, args.steps, args.warmup)
+    strings = float(1 << HEAD_N)
+    value = fams * strings / el
     out = {
-        "metric": "Pauli strings evaluated/sec (FWHT path)",
+        "metric": "Pauli strings evaluated/sec (FWHT path, % HBM peak); M_2 wall time at fixed std-err",
         "value": value,
         "unit": "Pauli strings/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * el64 / args.steps,
+        "ms_per_step": 1e3 * el / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "exact enumeration of all 4^20 Pauli strings of an N=20 T-doped random Clifford "
-                               "state (eta=20, N_T=20, from |0..0>), complex64 state, FP32 transform, FP64 sums",
-                   "n_qubits": n, "eta": ETA, "n_t": N_T, "seed": seed, "families_per_step": 1 << n,
-                   "outputs": "M_1, M_2, nullity" if args.max_alpha == 2 else "M_1, M_2, M_3, M_4, nullity",
-                   "pauli_strings_per_step": strings, "parallelism": "single GPU"},
-        "results_c64": {"M1": r64["M1"], "M2": r64["M"][0], "M3": r64["M"][1], "M4": r64["M"][2],
-                        "nullity": r64["nullity"], "P": r64["P"]},
-        "roofline": roofline,
+        "config": {"workload": "N=%d T-doped random Clifford state (eta=%d, N_T=%d, from |0..0>), complex64 (2 GiB), "
+                               "Clifford-preconditioned with %d brick-wall layers; Monte Carlo over x: x = 0 plus %d "
+                               "draws from the exact marginal per step, %d families per launch; FP32 transform, FP64 "
+                               "sums; outputs S_2, M_2, M_1 and their standard errors"
+                               % (HEAD_N, args.eta, 2 * HEAD_N, 2 * HEAD_N, HEAD_FAMILIES, HEAD_BATCH),
+                   "n_qubits": HEAD_N, "eta": args.eta, "n_t": 2 * HEAD_N, "seed": seed,
+                   "families_per_step": HEAD_FAMILIES + 1, "families_per_launch": HEAD_BATCH,
+                   "pauli_strings_per_step": (HEAD_FAMILIES + 1) * strings, "parallelism": "single GPU"},
+        "results": {"M2_last_step": last["M"][0], "M2_se_last_step": last["M_se"][0], "M1_last_step": last["M1"],
+                    "precondition_s": pre_s},
+        "roofline": headline_roofline(torch, kt),
     }
-    if r128 is not None:
-        out["c128"] = {"value": args.steps_c128 * strings / el128, "ms_per_step": 1e3 * el128 / args.steps_c128,
-                       "dtype": "f64", "M1": r128["M1"], "M2": r128["M"][0], "nullity": r128["nullity"],
-                       "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0]}
-    if not args.no_mc_leg:
-        out["m2_wall_time"] = [mc_leg(pw, torch, stream, eta, args.timing_every) for eta in args.mc_eta]
+    per_family_s = el / fams
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = headline_cpu_baseline(pw, ctx, seed, args.cpu_budget)
+    if args.sweep_steps > 0:
+        out["n20_exact"] = sweep20_leg(pw, torch, stream, args.sweep_steps, 1, args.steps_c128, args.timing_every,
+                                       args.max_alpha)
+    if not args.no_learned_leg and args.learned_leg:
+        out["learned_vs_plain"] = [learned_leg(pw, torch, stream, k, args.learned_draws, args.learned_pilot)
+                                   for k in args.learned_leg]
+    for eta in args.mc_eta:
+        out.setdefault("m2_wall_time_marginal", []).append(mc_leg(pw, torch, stream, eta, 1))
     if args.multistate_leg:
         out["multi_state"] = multistate_leg(pw, torch, stream)
     if args.mixed_leg:
         out["mixed_state"] = mixed_leg(pw, torch, stream)
     if args.haar_leg:
         out["haar_brickwall"] = haar_leg(pw, torch, stream, args.haar_draws)
-    if args.learned_leg is not None:
-        kinds = args.learned_leg or ["psi_m", "tdoped"]
-        out["learned_vs_plain"] = [learned_leg(pw, torch, stream, k, args.learned_draws, args.learned_pilot)
-                                   for k in kinds]
-    if not args.no_cpu_baseline:
-        import oracle
-        psi_host = psi128_dev.cpu().numpy()
-        # the oracle prepares its own copy of the state from the same gate list
-        psi_oracle = oracle.apply_gates(psi0, *gates)
-        out["cpu_baseline"] = cpu_baseline(psi_oracle, args.cpu_budget)
-        out["cpu_baseline"]["state_check_max_abs_diff"] = float(np.max(np.abs(psi_host - psi_oracle)))
+    if args.sigma_budget > 0:
+        left = args.total_budget - (time.perf_counter() - t_start)
+        budget = min(args.sigma_budget, max(10.0, left - 15.0))
+        out["m2_wall_time"] = sigma_leg(pw, torch, ctx, seed, budget, per_family_s, pre_s)
+    ctx.close()
+    out["bench_wall_s"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
 
 

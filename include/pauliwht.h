@@ -220,6 +220,22 @@ PW_API pw_status pw_exact(pw_ctx ctx, double eps, pw_result* out);
 PW_API pw_status pw_mc(pw_ctx ctx, pw_sampler sampler, double eps, int batch, uint64_t max_samples,
                 double target_se, uint64_t seed, pw_result* out);
 
+/* Monte Carlo with the sampler chosen from a pilot.  The number of families a target
+ * error needs grows as the square of the relative spread r_2 = sd(y)/S of the per-draw
+ * terms (Monte Carlo section, Eq. stdM), and which sampler spreads less depends on the
+ * state.  A pilot of `pilot` exact-marginal draws (Philox key seed ^ 0x50494C4F54; not
+ * counted in the result) estimates both spreads: the marginal's from its own terms
+ * (1 - p0) m_x / p(x), the uniform sampler's from the same draws reweighted to the uniform
+ * law (second moment sum_{x != 0} (d - 1) m_x^2 = E[(d - 1)(1 - p0) m_x^2 / p(x)]).  Since
+ * m_x <= p(x)/d, the families with large m_x that dominate the uniform sampler's variance
+ * are those the marginal draws most often, which a short uniform pilot tends to miss.
+ * The sampler with the smaller estimate runs pw_mc(ctx, chosen, eps, batch, max_samples,
+ * target_se, seed) -- bitwise that call's result.  A state whose marginal has no mass on
+ * x != 0 takes the uniform sampler.  Optional outputs: *chosen, pilot_r2[2] (uniform,
+ * marginal; NaN when the marginal pilot could not run). */
+PW_API pw_status pw_mc_auto(pw_ctx ctx, double eps, int batch, uint64_t max_samples, double target_se,
+                            uint64_t seed, int64_t pilot, pw_sampler* chosen, double* pilot_r2, pw_result* out);
+
 /* ---------------------------------------------------------------------------
  * Learned proposal over X-bitstrings (not in the paper; an importance-sampling
  * proposal for the Monte Carlo estimator).  A masked autoregressive network

@@ -21,7 +21,7 @@ __all__ = [
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
     "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_eval_x_noalloc", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_mc_auto", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
@@ -117,6 +117,8 @@ def _load():
         "pw_exact": ([_vp, _dbl, ctypes.POINTER(pw_result)], _int),
         "pw_mc": ([_vp, _int, _dbl, _int, _u64, _dbl, _u64, ctypes.POINTER(pw_result)], _int),
         "pw_set_moments": ([_vp, _int], _int),
+        "pw_mc_auto": ([_vp, _dbl, _int, _u64, _dbl, _u64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_dbl),
+                        ctypes.POINTER(pw_result)], _int),
         "pw_set_graphs": ([_vp, _int], _int),
         "pw_inject_fault": ([_vp, _int], _int),
         "pw_autotune": ([_vp, ctypes.POINTER(_int), _vp, _vp, ctypes.POINTER(_int)], _int),
@@ -283,6 +285,17 @@ def pw_mc(ctx, sampler, eps, batch, max_samples, target_se, seed):
     _check(_L.pw_mc(ctx, int(sampler), float(eps), int(batch), int(max_samples), float(target_se), int(seed),
                     ctypes.byref(r)))
     return r.as_dict()
+
+
+def pw_mc_auto(ctx, eps, batch, max_samples, target_se, seed, pilot):
+    """(result dict, chosen sampler, (pilot r_2 of the uniform sampler, of the marginal sampler),
+    both estimated from one exact-marginal pilot)."""
+    r = pw_result()
+    ch = _int()
+    r2 = (_dbl * 2)()
+    _check(_L.pw_mc_auto(ctx, float(eps), int(batch), int(max_samples), float(target_se), int(seed), int(pilot),
+                         ctypes.byref(ch), r2, ctypes.byref(r)))
+    return r.as_dict(), ch.value, tuple(r2)
 
 
 def pw_set_moments(ctx, max_alpha):

@@ -815,8 +815,24 @@ pw_status pw_exact(pw_ctx c, double eps, pw_result* out) {
     return PW_OK;
 }
 
+namespace {
+struct DrawMP {
+    double m2, p;
+};
+pw_status mc_core(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t max_samples, double target_se,
+                  uint64_t seed, pw_result* out, std::vector<DrawMP>* draws);
+}
+
 pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t max_samples, double target_se,
                 uint64_t seed, pw_result* out) {
+    return mc_core(c, sampler, eps, batch, max_samples, target_se, seed, out, nullptr);
+}
+
+namespace {
+// The estimator of pw_mc; with draws != nullptr each drawn family's m_{2;x} and p(x) are
+// also returned (the pilot of pw_mc_auto).
+pw_status mc_core(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t max_samples, double target_se,
+                  uint64_t seed, pw_result* out, std::vector<DrawMP>* draws) {
     pw_status s = check_state(c);
     if (s != PW_OK) return s;
     if (!out) return fail(PW_ERR_ARG, "null output");
@@ -880,6 +896,7 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
             const FamilyRes& f = res[i];
             const double w = sampler == PW_SAMPLER_UNIFORM_NZ ? (d - 1.0) : (1.0 - p0) / f.p;
             for (int a = 0; a < 3; ++a) run[a].add(w * f.m[a]);
+            if (draws) draws->push_back({f.m[0], f.p});
             run[3].add(w * f.ent);
             gap = fmax(gap, f.gap);
         }
@@ -915,6 +932,74 @@ pw_status pw_mc(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t ma
     r.n_samples = drawn + 1;
     r.gap = gap;
     *out = r;
+    return PW_OK;
+}
+
+// Relative spreads r = sd(y)/S of both samplers' per-draw terms (alpha = 2), from one
+// pilot of exact-marginal draws x_i ~ p(x | x != 0).  The marginal's terms are
+// y = (1 - p0) m_x / p(x) directly.  The uniform sampler's terms (d - 1) m_x have mean
+// S - m_0 as well, and second moment
+//     sum_{x != 0} (d - 1) m_x^2 = E_marginal[ (d - 1) (1 - p0) m_x^2 / p(x) ],
+// estimated from the same draws.  Since m_x <= p(x)/d (|F| <= 1), the marginal draws weight
+// every x by at least its share of that moment, so the rare families with large m_x that
+// dominate the uniform sampler's variance (and that a short uniform pilot usually misses)
+// are the ones the marginal draws most often.
+struct Spreads {
+    double r_uniform, r_marginal;
+};
+Spreads spreads_from_marginal_pilot(const std::vector<DrawMP>& v, double m0, double p0, double d) {
+    const double n = (double)v.size();
+    double sy = 0.0, syy = 0.0, su2 = 0.0;
+    for (const DrawMP& t : v) {
+        const double y = (1.0 - p0) * t.m2 / t.p;
+        sy += y;
+        syy += y * y;
+        su2 += (d - 1.0) * y * t.m2;
+    }
+    const double mu = sy / n;
+    const double S = m0 + mu;
+    Spreads sp;
+    sp.r_marginal = sqrt(fmax(syy / n - mu * mu, 0.0) * n / (n - 1.0)) / S;
+    sp.r_uniform = sqrt(fmax(su2 / n - mu * mu, 0.0) * n / (n - 1.0)) / S;
+    return sp;
+}
+}  // namespace
+
+pw_status pw_mc_auto(pw_ctx c, double eps, int batch, uint64_t max_samples, double target_se, uint64_t seed,
+                     int64_t pilot, pw_sampler* chosen, double* pilot_r2, pw_result* out) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (!out) return fail(PW_ERR_ARG, "null output");
+    if (pilot < 2) return fail(PW_ERR_ARG, "pilot must be >= 2 draws");
+    // pilot estimates of both samplers on their own Philox streams (keyed seed ^ "PILOT" + k),
+    // so that the estimate that follows draws independently of the choice
+    // one pilot of exact-marginal draws on its own Philox stream (key seed ^ "PILOT"), so that
+    // the estimate that follows draws independently of the choice
+    double r2[2] = {NAN, NAN};
+    const uint64_t pseed = seed ^ 0x50494C4F54ull;
+    std::vector<DrawMP> v;
+    pw_result pr;
+    s = mc_core(c, PW_SAMPLER_MARGINAL_NZ, eps, batch, (uint64_t)pilot + 1, 0.0, pseed, &pr, &v);
+    if (s == PW_OK) {
+        FamilyRes r0;
+        const uint64_t zero = 0;
+        s = eval_host(c, &zero, 1, eps, &r0);
+        if (s != PW_OK) return s;
+        const Spreads sp = spreads_from_marginal_pilot(v, r0.m[0], r0.p, ldexp(1.0, c->n));
+        r2[0] = sp.r_uniform;
+        r2[1] = sp.r_marginal;
+    } else if (s != PW_ERR_UNSUPPORTED) {
+        return s;   // PW_ERR_UNSUPPORTED: no mass on x != 0, only the uniform sampler runs
+    }
+    // the sample count for a target error grows as r_2^2 (Eq. stdM): the smaller spread wins
+    const pw_sampler pick = (r2[1] < r2[0]) ? PW_SAMPLER_MARGINAL_NZ : PW_SAMPLER_UNIFORM_NZ;
+    s = pw_mc(c, pick, eps, batch, max_samples, target_se, seed, out);
+    if (s != PW_OK) return s;
+    if (chosen) *chosen = pick;
+    if (pilot_r2) {
+        pilot_r2[0] = r2[0];
+        pilot_r2[1] = r2[1];
+    }
     return PW_OK;
 }
 
