@@ -74,6 +74,15 @@ typedef enum {
 
 typedef enum { PW_C128 = 0, PW_C64 = 1 } pw_dtype;
 
+/* Arithmetic of the product and the transform (pw_set_precision).  The reductions over z,
+ * the logarithms and the nullity test always accumulate in FP64. */
+typedef enum {
+    PW_PREC_AUTO = 0,    /* follows the storage: FP64 for complex128, FP32 for complex64       */
+    PW_PREC_F64 = 1,     /* FP64 (a complex64 state is widened into a library-owned copy)       */
+    PW_PREC_F32 = 2,     /* FP32 (a complex128 state is rounded into a library-owned copy)      */
+    PW_PREC_BF16X2 = 3   /* split-BF16 Hadamard blocks on the matrix cores, FP32 accumulate     */
+} pw_prec;
+
 typedef enum {
     PW_SAMPLER_UNIFORM_NZ = 0,  /* x uniform over F_2^N \ {0} (Monte Carlo section)  */
     PW_SAMPLER_MARGINAL_NZ = 1  /* x ~ p(x | x != 0), p the exact x-marginal          */
@@ -325,6 +334,23 @@ typedef struct {
 } pw_state_ref;
 PW_API pw_status pw_eval_states(pw_ctx ctx, int nstates, const pw_state_ref* states, const int* state_idx,
                                 const uint64_t* xs, int64_t n_x, double eps, pw_xres* out);
+
+/* Arithmetic of every later family evaluation of this context (pw_eval_x, pw_eval_x_device,
+ * pw_exact, pw_mc, pw_mc_auto, pw_mc_learned, pw_autotune); pw_family_values, pw_mixed,
+ * pw_eval_states and the samplers keep the storage precision.  A state stored in the other
+ * precision is converted into a library-owned device copy (2^n amplitudes) before the next
+ * evaluation and again after pw_apply_gates / pw_precondition; the workspace is planned for
+ * the compute precision (size a lent workspace with pw_workspace_size of that dtype).
+ * PW_PREC_BF16X2 (Eq. for the FWHT written as Hadamard blocks, H_16 = H^{(x)4}): the product
+ * is formed in FP32, and the low 8 index bits of every tile of the transform go through two
+ * 16 x 16 Hadamard steps on the matrix cores (v_mfma_f32_16x16x32_bf16) with each FP32 input
+ * split into two BF16 parts x = hi + lo (residual |x - hi - lo| <= 2^-18 |x|) and FP32
+ * accumulation; the other bits run as FP32 butterflies.  Error bound per value:
+ * |dF| <= (2 * 2^-18 + (n + 12) * 2^-24) * sum_b |f_x(b)| (<= that factor, Cauchy-Schwarz).
+ * The single-workgroup kernel (n - 1 <= 13) takes this path from n = 9; below that the FP32
+ * kernel runs.  Use a nullity tolerance of at least 1e-4 with PW_PREC_F32 or BF16X2; a
+ * nullity count that is not a power of two still returns PW_ERR_TOLERANCE from pw_exact. */
+PW_API pw_status pw_set_precision(pw_ctx ctx, pw_prec prec);
 
 /* Test support for the error paths: every later HIP call of one class made by this
  * context fails before it is issued (fault_class 1 = device or pinned allocation, 2 =

@@ -17,7 +17,8 @@ import numpy as np
 import torch  # noqa: F401,E402
 
 __all__ = [
-    "PWError", "PW_C128", "PW_C64", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
+    "PWError", "PW_C128", "PW_C64", "PW_PREC_AUTO", "PW_PREC_F64", "PW_PREC_F32", "PW_PREC_BF16X2",
+    "pw_set_precision", "PW_SAMPLER_UNIFORM_NZ", "PW_SAMPLER_MARGINAL_NZ", "XRES_DTYPE",
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
     "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_eval_x_noalloc", "pw_family_values",
@@ -30,6 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_NAME = "libpauliwht.so"
 
 PW_C128, PW_C64 = 0, 1
+PW_PREC_AUTO, PW_PREC_F64, PW_PREC_F32, PW_PREC_BF16X2 = 0, 1, 2, 3
 PW_SAMPLER_UNIFORM_NZ, PW_SAMPLER_MARGINAL_NZ = 0, 1
 STATUS = {0: "PW_OK", 1: "PW_ERR_ARG", 2: "PW_ERR_RANGE", 3: "PW_ERR_NOT_NORMALIZED", 4: "PW_ERR_NO_STATE",
           5: "PW_ERR_WORKSPACE", 6: "PW_ERR_HIP", 7: "PW_ERR_TOLERANCE", 8: "PW_ERR_UNSUPPORTED"}
@@ -121,6 +123,7 @@ def _load():
                         ctypes.POINTER(pw_result)], _int),
         "pw_set_graphs": ([_vp, _int], _int),
         "pw_inject_fault": ([_vp, _int], _int),
+        "pw_set_precision": ([_vp, _int], _int),
         "pw_autotune": ([_vp, ctypes.POINTER(_int), _vp, _vp, ctypes.POINTER(_int)], _int),
         "pw_eval_states": ([_vp, _int, _vp, _vp, _vp, _i64, _dbl, _vp], _int),
         "pw_mixed": ([_vp, _int, _dbl, ctypes.POINTER(pw_mixed_result)], _int),
@@ -325,6 +328,11 @@ def pw_eval_states(ctx, states, state_idx, xs, eps):
     _check(_L.pw_eval_states(ctx, len(states), arr, idx.ctypes.data, xs.ctypes.data, len(xs), float(eps),
                              out.ctypes.data))
     return out
+
+
+def pw_set_precision(ctx, prec):
+    """Arithmetic of later family evaluations (PW_PREC_AUTO, _F64, _F32, _BF16X2)."""
+    _check(_L.pw_set_precision(ctx, int(prec)))
 
 
 FAULT_CLASSES = {None: 0, "alloc": 1, "launch": 2, "copy": 3}

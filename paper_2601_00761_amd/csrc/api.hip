@@ -200,6 +200,15 @@ struct pw_ctx_s {
     bool capturing = false;
     // error-path testing (pw_inject_fault): the class of HIP call made to fail
     int fault_class = 0;
+    // transform arithmetic (pw_set_precision) and what the kernels read: the bound state,
+    // or a library-owned copy of it in the compute precision
+    int prec = PW_PREC_AUTO;
+    bool cdbl = false;           // FP64 kernels (complex128 input)
+    bool cmfma = false;          // split-BF16 matrix-core first pass / single-workgroup kernel
+    const void* cpsi = nullptr;
+    void* conv = nullptr;
+    size_t conv_bytes = 0;
+    bool conv_valid = false;
 };
 
 namespace {
@@ -208,6 +217,19 @@ namespace {
 // it is issued, set by pw_inject_fault for tests of the error paths.
 enum { FAULT_NONE = 0, FAULT_ALLOC = 1, FAULT_LAUNCH = 2, FAULT_COPY = 3 };
 inline bool fault(pw_ctx c, int cls) { return c->fault_class == cls; }
+
+// Storage dtype of the data the kernels read for a state of storage dtype dt.
+pw_dtype compute_dtype(pw_ctx c, pw_dtype dt) {
+    if (c->prec == PW_PREC_F64) return PW_C128;
+    if (c->prec == PW_PREC_F32 || c->prec == PW_PREC_BF16X2) return PW_C64;
+    return dt;
+}
+
+// Autotune key of the arithmetic: 0 FP64, 1 FP32, 2 split-BF16.
+int prec_key(pw_ctx c, pw_dtype dt) {
+    if (c->prec == PW_PREC_BF16X2) return 2;
+    return compute_dtype(c, dt) == PW_C128 ? 0 : 1;
+}
 
 hipEvent_t take_event(pw_ctx c) {
     if (!c->pool.empty()) {
@@ -247,15 +269,15 @@ const LaunchTimer* timer_of(pw_ctx c) { return (c->timing_every > 0 && !c->captu
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, int> g_tune;
 
-int tuned_batch(int device, int n, pw_dtype dt) {
+int tuned_batch(int device, int n, int key) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(std::make_tuple(device, n, (int)dt));
+    auto it = g_tune.find(std::make_tuple(device, n, key));
     return it == g_tune.end() ? 0 : it->second;
 }
 
-void set_tuned_batch(int device, int n, pw_dtype dt, int b) {
+void set_tuned_batch(int device, int n, int key, int b) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(device, n, (int)dt)] = b;
+    g_tune[std::make_tuple(device, n, key)] = b;
 }
 
 pw_status check_ctx(pw_ctx c) {
@@ -275,8 +297,10 @@ T* at(pw_ctx c, size_t off) {
     return reinterpret_cast<T*>(c->ws + off);
 }
 
-// Carve (or allocate) the workspace for the bound state.
-pw_status prepare_workspace(pw_ctx c, int n, pw_dtype dt) {
+// Carve (or allocate) the workspace for the bound state (storage dtype dt): sized and
+// planned for the compute precision.
+pw_status prepare_workspace(pw_ctx c, int n, pw_dtype sdt) {
+    const pw_dtype dt = compute_dtype(c, sdt);
     if (c->ws && !c->ws_owned) {
         int b = MAX_BATCH;
         while (b >= 1 && layout_for(n, dt, b).total > c->ws_bytes) b /= 2;
@@ -303,10 +327,38 @@ pw_status prepare_workspace(pw_ctx c, int n, pw_dtype dt) {
         }
     }
     c->L = layout_for(n, dt, c->batch);
-    c->P = make_plan(n, dt == PW_C128);
+    c->cmfma = c->prec == PW_PREC_BF16X2;
+    c->cdbl = dt == PW_C128;
+    c->P = c->cmfma ? make_plan_bf16x2(n) : make_plan(n, c->cdbl);
+    c->cpsi = dt == sdt ? c->psi : nullptr;
+    c->conv_valid = dt == sdt;
     c->run_batch = c->batch;
-    const int tuned = tuned_batch(c->device, n, dt);
+    const int tuned = tuned_batch(c->device, n, prec_key(c, sdt));
     if (tuned > 0 && tuned < c->batch) c->run_batch = tuned;
+    return PW_OK;
+}
+
+// The state in the compute precision: the bound buffer itself, or a library-owned copy
+// converted from it (made again after the state changes).
+pw_status ensure_compute_state(pw_ctx c) {
+    if (c->conv_valid) return PW_OK;
+    const pw_dtype cdt = c->cdbl ? PW_C128 : PW_C64;
+    const size_t need = ((size_t)1 << c->n) * esize(cdt);
+    if (!c->conv || c->conv_bytes < need) {
+        if (c->conv) {
+            PW_HIP(hipStreamSynchronize(c->stream));
+            PW_HIP(hipFree(c->conv));
+            c->conv = nullptr;
+            c->conv_bytes = 0;
+        }
+        if (fault(c, FAULT_ALLOC)) return fail(PW_ERR_HIP, "hipMalloc: injected failure");
+        PW_HIP(hipMalloc(&c->conv, need));
+        c->conv_bytes = need;
+    }
+    if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
+    PW_HIP(convert_state(c->dtype == PW_C128, c->psi, c->conv, c->n, c->stream));
+    c->cpsi = c->conv;
+    c->conv_valid = true;
     return PW_OK;
 }
 
@@ -332,7 +384,7 @@ pw_status run_norm(pw_ctx c, double* out) {
 // results to device array d_out, in launches of the context's launch batch, on st.
 pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
                        hipStream_t st) {
-    const bool dbl = c->dtype == PW_C128;
+    const bool dbl = c->cdbl;
     // multi-pass plans: batches leave their partials side by side, one finalize per group
     const bool defer = !c->P.fused;
     FamilyRes* parts = at<FamilyRes>(c, c->L.parts);
@@ -344,7 +396,7 @@ pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, 
             g0 = i;
             pending = 0;
         }
-        PW_HIP(eval_batch(c->P, dbl, c->max_alpha, c->psi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
+        PW_HIP(eval_batch(c->P, dbl, c->max_alpha, c->cpsi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
                           c->ws + c->L.work, parts + (size_t)pending * c->P.blocks_last, d_out + i, st,
                           timer_of(c), !defer));
         pending += nb;
@@ -356,7 +408,9 @@ pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, 
 pw_status eval_device_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
                          hipStream_t st) {
     if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
-    if (!d_xs || first_pass_group(c->P, c->dtype == PW_C128, c->run_batch) < 2)
+    const pw_status sc = ensure_compute_state(c);
+    if (sc != PW_OK) return sc;
+    if (!d_xs || first_pass_group(c->P, c->cdbl, c->run_batch) < 2)
         return eval_list_on(c, d_xs, x0, nx, eps, d_out, st);
     // tile-sharing groups: the list is evaluated in top-bit order, so that the families
     // of a launch share state tiles, and the results are put back in list order
@@ -490,6 +544,7 @@ pw_status pw_ctx_destroy(pw_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->made.block) (void)hipFree(c->made.block);
     if (c->rho) (void)hipFree(c->rho);
+    if (c->conv) (void)hipFree(c->conv);
     if (c->pin) (void)hipHostFree(c->pin);
     if (c->nrm) (void)hipFree(c->nrm);
     if (c->gstream) {
@@ -597,6 +652,7 @@ pw_status pw_apply_gates(pw_ctx c, int ng, const int* kinds, const int* qubits, 
         else PW_HIP(apply_diag(dbl, c->psi, c->n, qubits[2 * g], mats + 32 * g, c->stream));
     }
     c->cdf_valid = false;
+    c->conv_valid = c->cpsi == c->psi;
     PW_HIP(hipStreamSynchronize(c->stream));
     return PW_OK;
 }
@@ -690,6 +746,7 @@ pw_status pw_precondition(pw_ctx c, int n_layers, uint64_t seed) {
         }
     }
     c->cdf_valid = false;
+    c->conv_valid = c->cpsi == c->psi;
     PW_HIP(hipStreamSynchronize(c->stream));
     return PW_OK;
 }
@@ -1416,8 +1473,7 @@ pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per
     // candidate families per launch: powers of two up to the workspace batch, not below
     // the tile-sharing group of the first pass where the state has one (a smaller launch
     // would switch the groups off)
-    const bool dbl = c->dtype == PW_C128;
-    const int bmin = first_pass_group(c->P, dbl, 4);
+    const int bmin = first_pass_group(c->P, c->cdbl, 4);
     std::vector<int> cand;
     for (int b = c->batch; b >= bmin && (int)cand.size() < 6; b /= 2) cand.push_back(b);
     if (cand.empty()) cand.push_back(c->batch);
@@ -1469,7 +1525,7 @@ pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per
         return s;
     }
     c->run_batch = bestb;
-    set_tuned_batch(c->device, c->n, c->dtype, bestb);
+    set_tuned_batch(c->device, c->n, prec_key(c, c->dtype), bestb);
     *best_batch = bestb;
     if (n_candidates) *n_candidates = (int)times.size();
     for (size_t i = 0; i < times.size(); ++i) {
@@ -1597,12 +1653,17 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         c->psi = states[k].psi;
         c->n = states[k].n;
         c->dtype = states[k].dtype;
-        c->P = make_plan(c->n, c->dtype == PW_C128);
+        // each state in its own storage precision
+        c->cdbl = c->dtype == PW_C128;
+        c->cmfma = false;
+        c->cpsi = c->psi;
+        c->conv_valid = true;
+        c->P = make_plan(c->n, c->cdbl);
         const int B = Bk[(size_t)k];
         c->L = layout_for(c->n, c->dtype, B);
         if (c->L.total > cap) return fail(PW_ERR_WORKSPACE, "state %d does not fit the shared workspace", k);
         c->batch = B;
-        const int tuned = tuned_batch(c->device, c->n, c->dtype);
+        const int tuned = tuned_batch(c->device, c->n, c->cdbl ? 0 : 1);
         c->run_batch = tuned > 0 && tuned < B ? tuned : B;
         c->cdf_valid = false;
         return PW_OK;
@@ -1660,6 +1721,22 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
     s = restore(s);
     if (s != PW_OK) return s;
     for (int64_t j = 0; j < n_x; ++j) memcpy(out + order[(size_t)j], hres + j, sizeof(FamilyRes));
+    return PW_OK;
+}
+
+pw_status pw_set_precision(pw_ctx c, pw_prec prec) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (prec < PW_PREC_AUTO || prec > PW_PREC_BF16X2) return fail(PW_ERR_ARG, "unknown precision %d", (int)prec);
+    if (prec == c->prec) return PW_OK;
+    c->prec = prec;
+    if (c->bound) {
+        c->bound = false;   // re-plan (and re-carve) for the new arithmetic
+        c->cdf_valid = false;
+        s = prepare_workspace(c, c->n, c->dtype);
+        if (s != PW_OK) return s;
+        c->bound = true;
+    }
     return PW_OK;
 }
 

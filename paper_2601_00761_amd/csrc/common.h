@@ -55,9 +55,16 @@ struct Plan {
     int lo[4];
     int s[4];
     int blocks_last;   // workgroups per family in the final pass
+    // split-BF16 Hadamard blocks on the matrix cores for the single-workgroup transform and
+    // the first pass (single precision storage; column passes stay FP32 on the VALU)
+    bool mfma;
 };
 
 Plan make_plan(int n, bool dbl);
+// The plan of the split-BF16 matrix-core transform: single precision, the single-workgroup
+// kernel up to n - 1 = 13 bits (from n - 1 = 8; below that the FP32 kernel), else a 12-bit
+// first pass and FP32 column passes.
+Plan make_plan_bf16x2(int n);
 
 // Message buffer behind pw_last_error (thread-local).
 std::string& last_error_ref();
@@ -129,6 +136,9 @@ hipError_t reduce_sweep(const SweepSums* in, int64_t count, SweepSums* out, hipS
 hipError_t norm2(bool dbl, const void* psi, int n, double* d_partial, int nparts, double* d_out, unsigned* d_bad,
                  hipStream_t st);
 int norm2_parts(int n);
+// dst (2^n amplitudes) = src in the other precision: complex128 -> complex64 when src_dbl,
+// else complex64 -> complex128.
+hipError_t convert_state(bool src_dbl, const void* src, void* dst, int n, hipStream_t st);
 hipError_t apply_gate2(bool dbl, void* psi, int n, int q0, int q1, const double* m16 /*host*/, hipStream_t st);
 // Up to 6 two-qubit gates (local bit positions a[g], b[g] in [0, W + H), matrices
 // m32[32 g ..] host) in one pass over tiles of bits [0, W) and [hb, hb + H), W + H <= 12.

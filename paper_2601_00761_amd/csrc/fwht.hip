@@ -951,6 +951,217 @@ k_first_shared(const cx<R>* __restrict__ psi, int n, uint64_t x0, int fam, cx<R>
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 Hadamard blocks on the matrix cores
+// ---------------------------------------------------------------------------
+// v_mfma_f32_16x16x32_bf16 (one wave): lane l holds A[l mod 16][8 (l/16) + t] and
+// B[8 (l/16) + t][l mod 16], t = 0..7, and gets C[4 (l/16) + v][l mod 16], v = 0..3 (layout
+// checked on the device).  A 16 x 16 real block X is kept in the C layout: lane (g, c) =
+// (l/16, l mod 16) holds X[4g + v][c] in slot v.  Fed back as A with the K index
+// interleaved as k = 2 k16 + s, slot pairs (hi, lo) = the two BF16 parts of X[4g + v][c]
+// (x = hi + lo + r, |r| <= 2^-18 |x|), A[i][k16] = X[k16][i], and with B[2 k16 + s][j] =
+// H16[k16][j] (exact in BF16) the product is C = X^T H16 in FP32: C[i][j] = (H16 X)[j][i].
+// So one step transforms the 4 index bits held in (g, v) and leaves the result with those
+// bits in the lane (c) position and the other 4 bits in (g, v); a second step transforms
+// those, and the block is back in its starting layout with all 8 bits transformed.
+// Within a tile, point i of register (b, v) of lane (g, c) of wave w has index bits
+// c + 16 (4 g + v) + 256 (b + B w) before the exchange below.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// H16 as the B operand with the interleaved K index: B[8 g + t][j] = H16[4 g + t / 2][j].
+__device__ __forceinline__ bf16x8 h16_operand() {
+    const int l = threadIdx.x & 63;
+    const int j = l & 15, g = l >> 4;
+    bf16x8 h;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int k16 = 4 * g + (t >> 1);
+        h[t] = (__popc((unsigned)(k16 & j)) & 1) ? (__bf16)(-1.0f) : (__bf16)1.0f;
+    }
+    return h;
+}
+
+// One H16 step on the 16 x 16 real block x (C layout), hi / lo split, FP32 accumulation.
+__device__ __forceinline__ void h16_step(float (&x)[4], const bf16x8& h) {
+    bf16x8 a;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const __bf16 hi = (__bf16)x[v];
+        const __bf16 lo = (__bf16)(x[v] - (float)hi);
+        a[2 * v] = hi;
+        a[2 * v + 1] = lo;
+    }
+    mf4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h, acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = acc[v];
+}
+
+// Tile of 2^(8 + LB + LW) points: W = 2^LW waves, B = 2^LB blocks of 256 points per wave
+// (re / im [4 b + v]).  Bits 0..7 by two matrix-core steps per block and component, the
+// block bits by FP32 butterflies, then one LDS exchange moves the wave bits into the low
+// block-bit positions (LB >= LW) and FP32 butterflies finish them.  After the call, register
+// (b, v) of lane (g, c) of wave w holds index
+//     c + 16 (4 g + v) + 256 ((b & ~(W - 1)) | w) + 256 B (b & (W - 1)).
+template <int LB, int LW>
+struct MfmaTile {
+    static constexpr int B = 1 << LB, W = 1 << LW, K = 8 + LB + LW;
+    static_assert(LB >= LW, "the wave bits are exchanged into block-bit positions");
+    static constexpr int N = 4 * B;   // complex values per lane
+    // padded LDS index: 16 complex of padding per 64 points, so that the four 16-lane groups
+    // of a half wave (128 B each) fall on distinct banks
+    static __device__ __forceinline__ uint32_t pad(uint32_t i) { return i + ((i >> 6) << 4); }
+    static constexpr int lds_elems = (1 << K) + ((1 << K) >> 2);
+    static __device__ __forceinline__ uint32_t index_before(uint32_t w, uint32_t g, uint32_t c, int b, int v) {
+        return c + 16u * (4u * g + (uint32_t)v) + 256u * ((uint32_t)b + (uint32_t)B * w);
+    }
+    static __device__ __forceinline__ uint32_t index_after(uint32_t w, uint32_t g, uint32_t c, int b, int v) {
+        const uint32_t bb = ((uint32_t)b & ~(uint32_t)(W - 1)) | w;
+        return c + 16u * (4u * g + (uint32_t)v) + 256u * bb + 256u * (uint32_t)B * ((uint32_t)b & (uint32_t)(W - 1));
+    }
+    static __device__ __forceinline__ void butterflies(float (&re)[N], float (&im)[N], int bit) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (b & bit) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = 4 * b + v, k = 4 * (b | bit) + v;
+                const float ar = re[j], ai = im[j], br = re[k], bi = im[k];
+                re[j] = ar + br;
+                im[j] = ai + bi;
+                re[k] = ar - br;
+                im[k] = ai - bi;
+            }
+        }
+    }
+    static __device__ __forceinline__ void run(float (&re)[N], float (&im)[N], cx<float>* lds) {
+        const bf16x8 h = h16_operand();
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            float tr[4], ti[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                tr[v] = re[4 * b + v];
+                ti[v] = im[4 * b + v];
+            }
+            h16_step(tr, h);
+            h16_step(ti, h);
+            h16_step(tr, h);
+            h16_step(ti, h);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                re[4 * b + v] = tr[v];
+                im[4 * b + v] = ti[v];
+            }
+        }
+#pragma unroll
+        for (int bit = 1; bit < B; bit <<= 1) butterflies(re, im, bit);
+        if constexpr (LW > 0) {
+            const uint32_t l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4, c = l & 15;
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    cx<float> t;
+                    t.re = re[4 * b + v];
+                    t.im = im[4 * b + v];
+                    lds[pad(index_before(w, g, c, b, v))] = t;
+                }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const cx<float> t = lds[pad(index_after(w, g, c, b, v))];
+                    re[4 * b + v] = t.re;
+                    im[4 * b + v] = t.im;
+                }
+#pragma unroll
+            for (int bit = 1; bit < W; bit <<= 1) butterflies(re, im, bit);
+        }
+    }
+};
+
+// Products of the half-size problem at the tile-local indices of the matrix-core layout
+// (before the exchange): half index (tile << K) + index_before(...).
+template <class T>
+__device__ __forceinline__ void load_products_mfma(const cx<float>* __restrict__ psi, int nh, uint32_t x, uint32_t tile,
+                                                   float (&re)[T::N], float (&im)[T::N]) {
+    const uint32_t l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4, c = l & 15;
+    if (x != 0u) {
+        const int p = 31 - __builtin_clz(x);
+        const uint32_t lowmask = (1u << p) - 1u;
+#pragma unroll
+        for (int b = 0; b < T::B; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t bp = (tile << T::K) + T::index_before(w, g, c, b, v);
+                const uint32_t bb = (bp & lowmask) | ((bp & ~lowmask) << 1);
+                const cx<float> a = psi[bb];
+                const cx<float> q = psi[bb ^ x];
+                re[4 * b + v] = a.re * q.re + a.im * q.im;
+                im[4 * b + v] = a.re * q.im - a.im * q.re;
+            }
+    } else {
+        const uint32_t half = 1u << nh;
+#pragma unroll
+        for (int b = 0; b < T::B; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t bp = (tile << T::K) + T::index_before(w, g, c, b, v);
+                const cx<float> a = psi[bp];
+                const cx<float> q = psi[bp + half];
+                re[4 * b + v] = a.re * a.re + a.im * a.im;
+                im[4 * b + v] = q.re * q.re + q.im * q.im;
+            }
+    }
+}
+
+// Whole family in one workgroup on the matrix cores (n - 1 = K = 8 + LB + LW).
+template <int LB, int LW, int MOM>
+__global__ void __launch_bounds__(64 << LW)
+k_fused_mfma(const cx<float>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0, float eps,
+             FamilyRes* __restrict__ out) {
+    using T = MfmaTile<LB, LW>;
+    constexpr int NT = 64 << LW;
+    __shared__ cx<float> lds[LW > 0 ? T::lds_elems : 1];
+    __shared__ AccD shw[NT / 64];
+    const uint32_t slot = blockIdx.x;
+    const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);
+    float re[T::N], im[T::N];
+    load_products_mfma<T>(psi, n - 1, (uint32_t)x, 0u, re, im);
+    T::run(re, im, lds);
+    constexpr int RL = LB + 2;
+    const AccD tot = block_reduce<NT, MOM>(reduce_points<float, RL, MOM>(re, im, x == 0, eps, nullptr), shw);
+    if (threadIdx.x == 0) out[slot] = finish<MOM>(tot, x, n);
+}
+
+// First pass of a multi-pass transform on the matrix cores: products + the low 12 index
+// bits of one tile (4 waves x 4 blocks); the tile is written back in index order.
+__global__ void __launch_bounds__(256)
+k_first_mfma(const cx<float>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0,
+             cx<float>* __restrict__ work) {
+    using T = MfmaTile<2, 2>;
+    __shared__ cx<float> lds[T::lds_elems];
+    const int nh = n - 1;
+    const uint32_t tile = blockIdx.x, slot = blockIdx.y;
+    const uint32_t x = (uint32_t)((xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull));
+    float re[T::N], im[T::N];
+    load_products_mfma<T>(psi, nh, x, tile, re, im);
+    T::run(re, im, lds);
+    const uint32_t l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4, c = l & 15;
+    cx<float>* dst = work + ((size_t)slot << nh) + ((size_t)tile << T::K);
+#pragma unroll
+    for (int b = 0; b < T::B; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            cx<float> t;
+            t.re = re[4 * b + v];
+            t.im = im[4 * b + v];
+            dst[T::index_after(w, g, c, b, v)] = t;
+        }
+}
+
 // Column pass over index bits [lo, lo + S) of every family in the batch.
 // A tile is 2^S rows (stride 2^lo) by 2^W consecutive columns, W = K - S.
 // Grid: (2^(nh - K), families).  LAST: reduce to one partial per workgroup
@@ -1294,6 +1505,21 @@ hipError_t launch_column(int ktile, int s, int nh, int nb, cx<R>* work, int n, i
     return launch_column_t<R, 8, LAST, MOM>(s, grid, work, n, lo, xs, x0, eps, parts, st, tm);
 }
 
+template <int MOM>
+hipError_t launch_fused_mfma(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, float eps, FamilyRes* out,
+                             hipStream_t st, const LaunchTimer* tm) {
+    switch (n - 1) {
+#define PW_MF(K, LB, LW)                                                                                           \
+    case K:                                                                                                        \
+        PW_LAUNCH(tm, 0, nb, (k_fused_mfma<LB, LW, MOM>), dim3(nb), dim3(64 << LW), st, (const cx<float>*)psi, n, xs, \
+                  x0, eps, out);                                                                                   \
+        return hipGetLastError();
+        PW_MF(8, 0, 0) PW_MF(9, 1, 0) PW_MF(10, 2, 0) PW_MF(11, 2, 1) PW_MF(12, 2, 2) PW_MF(13, 3, 2)
+#undef PW_MF
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // First pass over nb families, with the tile-sharing groups where first_pass_group
 // asks for them.
 template <typename R, int TL, int RL, bool SPLIT>
@@ -1319,9 +1545,18 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
                         bool finalize) {
     if (nb <= 0) return hipSuccess;
     const R e = (R)eps;
+    if constexpr (sizeof(R) == 4) {
+        if (P.fused && P.mfma && P.nh >= 8) return launch_fused_mfma<MOM>(psi, P.n, xs, x0, nb, e, out, st, tm);
+    }
     if (P.fused) return launch_fused<R, MOM>(psi, P.n, xs, x0, nb, e, out, st, tm);
     const uint32_t tiles = 1u << (P.nh - P.k1);
     if constexpr (sizeof(R) == 4) {
+        if (P.mfma) {
+            if (P.k1 != K_FIRST) return hipErrorInvalidValue;
+            PW_LAUNCH(tm, 1, nb, k_first_mfma, dim3(tiles, nb), dim3(256), st, (const cx<float>*)psi, P.n, xs, x0,
+                      (cx<float>*)work);
+            goto first_done;
+        }
         if (P.k1 == 15) {
             launch_first<float, 10, 5, true>(P, psi, xs, x0, nb, work, st, tm);
             goto first_done;
@@ -1405,7 +1640,20 @@ hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* wor
 
 }  // namespace
 
-Plan make_plan(int n, bool dbl) {
+namespace {
+Plan make_plan_impl(int n, bool dbl, bool allow15);
+}
+
+Plan make_plan(int n, bool dbl) { return make_plan_impl(n, dbl, true); }
+
+Plan make_plan_bf16x2(int n) {
+    Plan P = make_plan_impl(n, false, false);
+    P.mfma = true;
+    return P;
+}
+
+namespace {
+Plan make_plan_impl(int n, bool dbl, bool allow15) {
     Plan P{};
     P.n = n;
     P.nh = n - 1;
@@ -1418,7 +1666,7 @@ Plan make_plan(int n, bool dbl) {
         return P;
     }
     P.fused = false;
-    if (!dbl && P.nh >= 22 && P.nh <= 27) {
+    if (!dbl && allow15 && P.nh >= 22 && P.nh <= 27) {
         // single precision, n = 23..28: a 15-bit first pass leaves one column pass
         P.k1 = 15;
         P.npass = 1;
@@ -1452,6 +1700,7 @@ Plan make_plan(int n, bool dbl) {
     P.blocks_last = 1 << (P.nh - ktile);
     return P;
 }
+}  // namespace
 
 hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, const uint64_t* xs, uint64_t x0,
                       int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
@@ -1531,7 +1780,7 @@ hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, 
 int first_pass_group(const Plan& P, bool dbl, int nb) {
     // states of 16 MiB and more (measured: 4-21 % less time per family from 16 MiB to
     // 8 GiB); at least 8 tiles per family, which the grouped numbering needs
-    if (P.fused || P.nh - P.k1 < 3 || ((size_t)(dbl ? 16 : 8) << P.n) < ((size_t)16 << 20)) return 1;
+    if (P.fused || P.mfma || P.nh - P.k1 < 3 || ((size_t)(dbl ? 16 : 8) << P.n) < ((size_t)16 << 20)) return 1;
     return nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
 }
 

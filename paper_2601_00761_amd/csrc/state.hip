@@ -254,6 +254,30 @@ hipError_t norm2(bool dbl, const void* psi, int n, double* d_partial, int nparts
     return hipGetLastError();
 }
 
+namespace {
+// dst = src converted amplitude by amplitude (complex128 <-> complex64, round to nearest).
+template <typename S, typename D>
+__global__ void __launch_bounds__(256) k_convert(const cx<S>* __restrict__ src, cx<D>* __restrict__ dst, uint64_t d) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= d) return;
+    const cx<S> v = src[i];
+    cx<D> o;
+    o.re = (D)v.re;
+    o.im = (D)v.im;
+    dst[i] = o;
+}
+}  // namespace
+
+hipError_t convert_state(bool src_dbl, const void* src, void* dst, int n, hipStream_t st) {
+    const uint64_t d = 1ull << n;
+    const dim3 grid((unsigned)((d + 255) / 256));
+    if (src_dbl)
+        hipLaunchKernelGGL((k_convert<double, float>), grid, dim3(256), 0, st, (const cx<double>*)src, (cx<float>*)dst, d);
+    else
+        hipLaunchKernelGGL((k_convert<float, double>), grid, dim3(256), 0, st, (const cx<float>*)src, (cx<double>*)dst, d);
+    return hipGetLastError();
+}
+
 hipError_t apply_gate2(bool dbl, void* psi, int n, int q0, int q1, const double* m16, hipStream_t st) {
     return dbl ? gate2_t<double>(psi, n, q0, q1, m16, st) : gate2_t<float>(psi, n, q0, q1, m16, st);
 }

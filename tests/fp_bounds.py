@@ -23,6 +23,14 @@ def gamma(n):
     return (n + 2) * U32
 
 
+def gamma_bf16x2(n):
+    """Split-BF16 path: two matrix-core H16 steps per tile with x = hi + lo + r,
+    |r| <= 2^-18 |x| (each step adds at most 2^-18 sum_b |f_x(b)| to every value), the FP32
+    butterflies and products as above, and the FP32 accumulation inside the matrix-core
+    steps (32-term sums, <= 5 u each of 2 steps)."""
+    return 2 * 2.0 ** -18 + (n + 12) * U32
+
+
 def family_bounds(F, n):
     """Bounds for one family from its exact spectrum F (complex array over z)."""
     a = np.abs(F)
@@ -40,12 +48,13 @@ def family_bounds(F, n):
     return out
 
 
-def family_bounds_from_sums(r, i, n):
+def family_bounds_from_sums(r, i, n, g=None):
     """The same bounds from the oracle's per-family sums (oracle.eval_x_with_bound_sums,
-    family i): no spectrum needs to be held in the test."""
+    family i): no spectrum needs to be held in the test.  g overrides the per-value
+    factor gamma(n) (e.g. gamma_bf16x2(n))."""
     b = r["bsum"][i]
     d = float(2 ** n)
-    g = gamma(n)
+    g = gamma(n) if g is None else g
     acc = 32 * U32
     out = {"gamma": g}
     out["p"] = 2 * g * b[0] / d + acc * r["p"][i]
