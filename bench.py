@@ -328,7 +328,10 @@ def multistate_leg(pw, torch, stream):
     pw.pw_set_moments(ctx.h, 2)
     out = {}
     res = {}
-    for name, states, dt, eps in (("c64", st64, pw.PW_C64, 1e-4), ("c128", st128, pw.PW_C128, 1e-7)):
+    for name, states, dt, eps, prec in (("c64", st64, pw.PW_C64, 1e-4, pw.PW_PREC_AUTO),
+                                        ("bf16x2", st64, pw.PW_C64, 1e-4, pw.PW_PREC_BF16X2),
+                                        ("c128", st128, pw.PW_C128, 1e-7, pw.PW_PREC_AUTO)):
+        pw.pw_set_precision(ctx.h, prec)
         refs = [(t, n, dt) for t, n in zip(states, ns)]
         pw.pw_eval_states(ctx.h, refs, idx[:MULTI_X], xs[:MULTI_X], eps)      # warm-up: workspace, kernels
         torch.cuda.synchronize()
@@ -338,13 +341,15 @@ def multistate_leg(pw, torch, stream):
         el = time.perf_counter() - t0
         res[name] = r
         out[name] = {"seconds": el, "pauli_strings_per_s": strings / el}
+    pw.pw_set_precision(ctx.h, pw.PW_PREC_AUTO)
     ctx.close()
     per = []
     for k, n in enumerate(ns):
         sl = slice(k * MULTI_X, (k + 1) * MULTI_X)
-        m32, m64 = res["c64"]["m"][sl, 0], res["c128"]["m"][sl, 0]
+        m32, m64, mbf = res["c64"]["m"][sl, 0], res["c128"]["m"][sl, 0], res["bf16x2"]["m"][sl, 0]
         e = {"n": n, "kind": kinds[k],
-             "max_rel_m2_fp32_vs_fp64": float(np.max(np.abs(m32 - m64) / np.maximum(np.abs(m64), 1e-300)))}
+             "max_rel_m2_fp32_vs_fp64": float(np.max(np.abs(m32 - m64) / np.maximum(np.abs(m64), 1e-300))),
+             "max_rel_m2_bf16x2_vs_fp64": float(np.max(np.abs(mbf - m64) / np.maximum(np.abs(m64), 1e-300)))}
         if n <= 20:
             psi = st128[k].cpu().numpy()
             o = oracle.eval_x(psi, xs[sl][[0, 1]], eps=1e-7, max_alpha=2)
@@ -357,6 +362,7 @@ def multistate_leg(pw, torch, stream):
                             "exact-marginal draws per state, one pw_eval_states call",
                 "n_values": ns, "families": len(xs), "pauli_strings": strings,
                 "max_rel_m2_fp32_vs_fp64": max(p["max_rel_m2_fp32_vs_fp64"] for p in per),
+                "max_rel_m2_bf16x2_vs_fp64": max(p["max_rel_m2_bf16x2_vs_fp64"] for p in per),
                 "max_rel_m2_fp64_vs_oracle": max(p.get("oracle_max_rel_m2_fp64", 0.0) for p in per),
                 "max_rel_m2_fp32_vs_oracle": max(p.get("oracle_max_rel_m2_fp32", 0.0) for p in per),
                 "per_state": per})
@@ -603,10 +609,11 @@ def sweep20_leg(pw, torch, stream, steps, warmup, steps_c128, timing_every, max_
     torch.cuda.synchronize()
     strings = float(1 << n) ** 2
 
-    def run(dtype, psi_dev, st, wu, eps, timing):
+    def run(dtype, psi_dev, st, wu, eps, timing, prec=pw.PW_PREC_AUTO):
         ctx = pw.Context(0, stream)
         pw.pw_set_moments(ctx.h, max_alpha)
         ctx.bind(psi_dev, dtype)
+        pw.pw_set_precision(ctx.h, prec)
         for _ in range(wu):
             ctx.exact(eps)
         if timing:
@@ -629,16 +636,21 @@ def sweep20_leg(pw, torch, stream, steps, warmup, steps_c128, timing_every, max_
         return el, last, kt
 
     el64, r64, kt64 = run(pw.PW_C64, psi64, steps, warmup, 1e-4, True)
+    elbf, rbf, ktbf = run(pw.PW_C64, psi64, steps, warmup, 1e-4, True, pw.PW_PREC_BF16X2)
     out = {"workload": "exact enumeration of all 4^20 Pauli strings of an N=20 T-doped random Clifford state "
                        "(eta=20, N_T=20, from |0..0>)",
            "c64": {"pauli_strings_per_s": steps * strings / el64, "ms_per_step": 1e3 * el64 / steps, "steps": steps,
                    "dtype": "f32", "M1": r64["M1"], "M2": r64["M"][0], "nullity": r64["nullity"], "P": r64["P"],
-                   "kernel_avg_us": kt64}}
+                   "kernel_avg_us": kt64},
+           "bf16x2": {"pauli_strings_per_s": steps * strings / elbf, "ms_per_step": 1e3 * elbf / steps,
+                      "steps": steps, "dtype": "bf16x2 (split-BF16 matrix-core first pass, FP32 column pass)",
+                      "M1": rbf["M1"], "M2": rbf["M"][0], "nullity": rbf["nullity"], "kernel_avg_us": ktbf}}
     if steps_c128 > 0:
         el128, r128, _ = run(pw.PW_C128, psi128, steps_c128, 1, 1e-7, False)
         out["c128"] = {"pauli_strings_per_s": steps_c128 * strings / el128, "ms_per_step": 1e3 * el128 / steps_c128,
                        "steps": steps_c128, "dtype": "f64", "M1": r128["M1"], "M2": r128["M"][0],
-                       "nullity": r128["nullity"], "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0]}
+                       "nullity": r128["nullity"], "dM2_c64_vs_c128": r64["M"][0] - r128["M"][0],
+                       "dM2_bf16x2_vs_c128": rbf["M"][0] - r128["M"][0]}
     prep.close()
     return out
 

@@ -336,8 +336,9 @@ PW_API pw_status pw_eval_states(pw_ctx ctx, int nstates, const pw_state_ref* sta
                                 const uint64_t* xs, int64_t n_x, double eps, pw_xres* out);
 
 /* Arithmetic of every later family evaluation of this context (pw_eval_x, pw_eval_x_device,
- * pw_exact, pw_mc, pw_mc_auto, pw_mc_learned, pw_autotune); pw_family_values, pw_mixed,
- * pw_eval_states and the samplers keep the storage precision.  A state stored in the other
+ * pw_exact, pw_mc, pw_mc_auto, pw_mc_learned, pw_autotune); pw_family_values, pw_mixed and
+ * the samplers keep the storage precision, and pw_eval_states evaluates every state in its
+ * storage precision except that complex64 states follow PW_PREC_BF16X2.  A state stored in the other
  * precision is converted into a library-owned device copy (2^n amplitudes) before the next
  * evaluation and again after pw_apply_gates / pw_precondition; the workspace is planned for
  * the compute precision (size a lent workspace with pw_workspace_size of that dtype).

@@ -1653,17 +1653,18 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         c->psi = states[k].psi;
         c->n = states[k].n;
         c->dtype = states[k].dtype;
-        // each state in its own storage precision
+        // each state in its own storage precision (complex64 states take the split-BF16
+        // transform when the context asks for it)
         c->cdbl = c->dtype == PW_C128;
-        c->cmfma = false;
+        c->cmfma = !c->cdbl && c->prec == PW_PREC_BF16X2;
         c->cpsi = c->psi;
         c->conv_valid = true;
-        c->P = make_plan(c->n, c->cdbl);
+        c->P = c->cmfma ? make_plan_bf16x2(c->n) : make_plan(c->n, c->cdbl);
         const int B = Bk[(size_t)k];
         c->L = layout_for(c->n, c->dtype, B);
         if (c->L.total > cap) return fail(PW_ERR_WORKSPACE, "state %d does not fit the shared workspace", k);
         c->batch = B;
-        const int tuned = tuned_batch(c->device, c->n, c->cdbl ? 0 : 1);
+        const int tuned = tuned_batch(c->device, c->n, c->cdbl ? 0 : c->cmfma ? 2 : 1);
         c->run_batch = tuned > 0 && tuned < B ? tuned : B;
         c->cdf_valid = false;
         return PW_OK;
