@@ -308,14 +308,34 @@ typedef struct {
 } pw_mixed_result;
 PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out);
 
-/* Autotuning of families per launch for the bound state: times the evaluation of a
- * list of uniformly drawn x (4 x the workspace batch, at most 4096; the sorted, grouped
- * path that Monte Carlo steps and device lists take) at up to 6 candidate launch sizes
- * (the workspace batch and its halvings, none below the first pass's tile-sharing group
- * where the state has one), keeps the fastest for this context and records it for later
- * binds of the same (device, n, dtype) in this process.
- * Optional outputs: candidates[i], us_per_family[i] (arrays of >= 6), n_candidates. */
+/* Autotuning of the transform schedule of the bound state, timed on a list of uniformly
+ * drawn x (4 x the workspace batch, at most 4096; the sorted, grouped path that Monte Carlo
+ * steps and device lists take).  Stage 1, at the workspace's launch size: every plan
+ * variant that applies -- first pass over the low 12 index bits, or (single precision,
+ * n - 1 = 16..27) over 15 bits; column tiles of 12 or 13 bits (single precision), or of
+ * 15 bits after a 15-bit first pass -- crossed with first-pass tile-sharing groups of 1, 2,
+ * 4 and 8 families.  Stage 2, for the fastest: up to 6 launch sizes (the workspace batch
+ * and its halvings, none below the group).  The result is recorded per (device, n,
+ * arithmetic) for every context of the process (pw_autotune_save / pw_autotune_load keep
+ * it across processes) and takes effect on this context unless pw_set_schedule fixed one.
+ * Results do not depend on the launch size or the group; the plan variant changes the
+ * order of the FP32 roundings only.  Optional outputs (stage 2): candidates[i],
+ * us_per_family[i] (arrays of >= 6), n_candidates. */
 PW_API pw_status pw_autotune(pw_ctx ctx, int* best_batch, int* candidates, double* us_per_family, int* n_candidates);
+
+/* Fix the schedule of this context (0 = the tuned or default choice for that part):
+ * first_bits 12 or 15, column_tile_bits 12, 13 or 15, group 1, 2, 4 or 8 families per
+ * first-pass tile-sharing group, batch families per launch (at most the workspace's).
+ * PW_ERR_UNSUPPORTED when the schedule does not apply to the bound state; a later bind of a
+ * state it does not apply to takes the default plan. */
+PW_API pw_status pw_set_schedule(pw_ctx ctx, int first_bits, int column_tile_bits, int group, int batch);
+/* The schedule in effect for the bound state (0 for the single-workgroup plans). */
+PW_API pw_status pw_get_schedule(pw_ctx ctx, int* first_bits, int* column_tile_bits, int* group, int* batch);
+/* Write every tuned schedule of the process to a text file (one line per device
+ * architecture, n and arithmetic), or read such a file and take its entries for the
+ * visible devices of the same architecture (*loaded = entries taken). */
+PW_API pw_status pw_autotune_save(const char* path);
+PW_API pw_status pw_autotune_load(const char* path, int* loaded);
 
 /* Several states of different sizes in one call: family xs[i] of state
  * states[state_idx[i]], results to out[i] (host arrays).  One workspace serves all

@@ -22,7 +22,7 @@ __all__ = [
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
     "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_eval_x_noalloc", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "pw_mc_auto", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_mc_auto", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_set_schedule", "pw_get_schedule", "pw_autotune_save", "pw_autotune_load", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
@@ -124,6 +124,11 @@ def _load():
         "pw_set_graphs": ([_vp, _int], _int),
         "pw_inject_fault": ([_vp, _int], _int),
         "pw_set_precision": ([_vp, _int], _int),
+        "pw_set_schedule": ([_vp, _int, _int, _int, _int], _int),
+        "pw_get_schedule": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                             ctypes.POINTER(_int)], _int),
+        "pw_autotune_save": ([ctypes.c_char_p], _int),
+        "pw_autotune_load": ([ctypes.c_char_p, ctypes.POINTER(_int)], _int),
         "pw_autotune": ([_vp, ctypes.POINTER(_int), _vp, _vp, ctypes.POINTER(_int)], _int),
         "pw_eval_states": ([_vp, _int, _vp, _vp, _vp, _i64, _dbl, _vp], _int),
         "pw_mixed": ([_vp, _int, _dbl, ctypes.POINTER(pw_mixed_result)], _int),
@@ -313,6 +318,27 @@ def pw_autotune(ctx):
     nc = _int()
     _check(_L.pw_autotune(ctx, ctypes.byref(best), cand, us, ctypes.byref(nc)))
     return best.value, {cand[i]: us[i] for i in range(nc.value)}
+
+
+def pw_set_schedule(ctx, first_bits=0, column_tile_bits=0, group=0, batch=0):
+    _check(_L.pw_set_schedule(ctx, int(first_bits), int(column_tile_bits), int(group), int(batch)))
+
+
+def pw_get_schedule(ctx):
+    """(first_bits, column_tile_bits, group, batch) in effect."""
+    v = [_int() for _ in range(4)]
+    _check(_L.pw_get_schedule(ctx, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def pw_autotune_save(path):
+    _check(_L.pw_autotune_save(os.fsencode(path)))
+
+
+def pw_autotune_load(path):
+    n = _int()
+    _check(_L.pw_autotune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 def pw_eval_states(ctx, states, state_idx, xs, eps):

@@ -86,7 +86,9 @@ Layout layout_for(int n, pw_dtype dt, int batch) {
     L.work = off;
     off += align256(work);
     L.parts = off;
-    const size_t per_batch = (size_t)batch * (size_t)P.blocks_last * sizeof(FamilyRes);
+    // final-pass partials: as many as the smallest column tile (2^12 points) of any schedule
+    const size_t blocks = P.fused ? 1 : ((size_t)1 << (P.nh - 12));
+    const size_t per_batch = (size_t)batch * blocks * sizeof(FamilyRes);
     size_t group = P.fused ? 1 : PARTS_BYTES_MAX / per_batch;
     if (group < 1) group = 1;
     if (group > (size_t)PARTS_GROUP_MAX) group = PARTS_GROUP_MAX;
@@ -209,6 +211,9 @@ struct pw_ctx_s {
     void* conv = nullptr;
     size_t conv_bytes = 0;
     bool conv_valid = false;
+    // schedule asked for by pw_set_schedule (zeros: the tuned or default choice)
+    Schedule sched{0, 0, 0};
+    int sched_batch = 0;
 };
 
 namespace {
@@ -264,20 +269,28 @@ void timer_commit(void* self, int k, int families, hipEvent_t a, hipEvent_t b) {
 
 const LaunchTimer* timer_of(pw_ctx c) { return (c->timing_every > 0 && !c->capturing) ? &c->timer : nullptr; }
 
-// Autotuned families-per-launch, per (device, n, dtype), shared by the contexts of
-// the process.
+// Autotuned schedules (plan variant, first-pass group, families per launch) per (device,
+// n, arithmetic), shared by the contexts of the process; pw_autotune_save / _load keep
+// them in a text file.
+struct Tuned {
+    Schedule sc;
+    int batch;
+    double us;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int>, Tuned> g_tune;
 
-int tuned_batch(int device, int n, int key) {
+bool tuned_get(int device, int n, int key, Tuned* t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(std::make_tuple(device, n, key));
-    return it == g_tune.end() ? 0 : it->second;
+    if (it == g_tune.end()) return false;
+    *t = it->second;
+    return true;
 }
 
-void set_tuned_batch(int device, int n, int key, int b) {
+void tuned_put(int device, int n, int key, const Tuned& t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(device, n, key)] = b;
+    g_tune[std::make_tuple(device, n, key)] = t;
 }
 
 pw_status check_ctx(pw_ctx c) {
@@ -295,6 +308,24 @@ pw_status check_state(pw_ctx c) {
 template <typename T>
 T* at(pw_ctx c, size_t off) {
     return reinterpret_cast<T*>(c->ws + off);
+}
+
+// Plan and launch size of the bound state: the context's own schedule when it applies,
+// else the process's tuned one, else the defaults.
+void apply_schedule(pw_ctx c, pw_dtype sdt) {
+    const int n = c->n;
+    Tuned t{};
+    const bool have_tuned = tuned_get(c->device, n, prec_key(c, sdt), &t);
+    const bool own = c->sched.first_bits || c->sched.column_tile_bits || c->sched.group;
+    Schedule sc = own ? c->sched : (have_tuned ? t.sc : Schedule{0, 0, 0});
+    if (c->cmfma) {
+        c->P = make_plan_bf16x2(n);
+    } else {
+        bool ok = true;
+        c->P = make_plan_sched(n, c->cdbl, sc, &ok);
+    }
+    int b = c->sched_batch ? c->sched_batch : (have_tuned ? t.batch : 0);
+    c->run_batch = (b > 0 && b < c->batch) ? b : c->batch;
 }
 
 // Carve (or allocate) the workspace for the bound state (storage dtype dt): sized and
@@ -329,12 +360,9 @@ pw_status prepare_workspace(pw_ctx c, int n, pw_dtype sdt) {
     c->L = layout_for(n, dt, c->batch);
     c->cmfma = c->prec == PW_PREC_BF16X2;
     c->cdbl = dt == PW_C128;
-    c->P = c->cmfma ? make_plan_bf16x2(n) : make_plan(n, c->cdbl);
     c->cpsi = dt == sdt ? c->psi : nullptr;
     c->conv_valid = dt == sdt;
-    c->run_batch = c->batch;
-    const int tuned = tuned_batch(c->device, n, prec_key(c, sdt));
-    if (tuned > 0 && tuned < c->batch) c->run_batch = tuned;
+    apply_schedule(c, sdt);
     return PW_OK;
 }
 
@@ -1465,18 +1493,51 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
     return PW_OK;
 }
 
+namespace {
+// Candidate schedules of the bound state: the plan variants that apply (first pass of 12 or
+// 15 bits, column tiles of 12 / 13 / 15 bits) crossed with the first-pass groups that the
+// plan and the launch size allow.
+std::vector<Schedule> schedule_candidates(pw_ctx c) {
+    std::vector<Schedule> out;
+    if (c->P.fused || c->cmfma) {
+        out.push_back(Schedule{0, 0, 0});
+        return out;
+    }
+    const int nh = c->n - 1;
+    std::vector<std::pair<int, int>> plans;
+    if (c->cdbl) {
+        plans.push_back({12, 12});
+    } else {
+        plans.push_back({12, 12});
+        plans.push_back({12, 13});
+        const int sb = nh - 15;
+        if (sb >= 1 && sb <= 12) {
+            if (sb <= 8) plans.push_back({15, 12});
+            if (sb <= 9) plans.push_back({15, 13});
+            if (sb >= 9) plans.push_back({15, 15});
+        }
+    }
+    for (auto& pk : plans) {
+        bool ok = true;
+        const Plan P = make_plan_sched(c->n, c->cdbl, Schedule{pk.first, pk.second, 1}, &ok);
+        if (!ok) continue;
+        const bool can_group = P.nh - P.k1 >= 3;
+        for (int g : {1, 2, 4, 8}) {
+            if (g > 1 && (!can_group || g > c->batch)) continue;
+            out.push_back(Schedule{pk.first, pk.second, g});
+        }
+    }
+    return out;
+}
+}  // namespace
+
 pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per_family, int* n_candidates) {
     pw_status s = check_state(c);
     if (s != PW_OK) return s;
     if (!best_batch) return fail(PW_ERR_ARG, "null output");
     if (fault(c, FAULT_LAUNCH)) return fail(PW_ERR_HIP, "kernel launch: injected failure");
-    // candidate families per launch: powers of two up to the workspace batch, not below
-    // the tile-sharing group of the first pass where the state has one (a smaller launch
-    // would switch the groups off)
-    const int bmin = first_pass_group(c->P, c->cdbl, 4);
-    std::vector<int> cand;
-    for (int b = c->batch; b >= bmin && (int)cand.size() < 6; b /= 2) cand.push_back(b);
-    if (cand.empty()) cand.push_back(c->batch);
+    s = ensure_compute_state(c);
+    if (s != PW_OK) return s;
     // the timed work is what Monte Carlo steps and device lists run: a list of uniformly
     // drawn x (Philox stream keyed 0x7475) through the sorted, grouped evaluation
     const uint64_t d = 1ull << c->n;
@@ -1489,49 +1550,163 @@ pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per
     hipEvent_t e0, e1;
     PW_HIP(hipEventCreate(&e0));
     PW_HIP(hipEventCreate(&e1));
+    const Plan saved_P = c->P;
     const int saved = c->run_batch;
     const int saved_every = c->timing_every;
     c->timing_every = 0;
-    double best = 1e300;
-    int bestb = c->batch;
-    std::vector<double> times;
     FamilyRes* fam = at<FamilyRes>(c, c->L.fam);
-    for (int b : cand) {
-        c->run_batch = b;
+    // microseconds per family of the current plan and launch size (best of two after a warm-up)
+    auto time_it = [&](double* us) -> pw_status {
         double tmin = 1e300;
-        for (int rep = 0; rep < 3; ++rep) {   // first repetition warms up
+        for (int rep = 0; rep < 3; ++rep) {
             PW_HIP(hipEventRecord(e0, c->stream));
-            s = eval_device(c, dx, 0, total, 1e-4, fam);
-            if (s != PW_OK) break;
+            const pw_status st = eval_device(c, dx, 0, total, 1e-4, fam);
+            if (st != PW_OK) return st;
             PW_HIP(hipEventRecord(e1, c->stream));
             PW_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             PW_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (rep > 0) tmin = fmin(tmin, (double)ms);
         }
+        *us = 1e3 * tmin / (double)total;
+        return PW_OK;
+    };
+    // stage 1: plan variant and group at the workspace's launch size
+    Schedule best_sc{0, 0, 0};
+    double best = 1e300;
+    c->run_batch = c->batch;
+    for (const Schedule& sc : schedule_candidates(c)) {
+        bool ok = true;
+        c->P = c->cmfma ? make_plan_bf16x2(c->n) : make_plan_sched(c->n, c->cdbl, sc, &ok);
+        double us = 0.0;
+        s = time_it(&us);
         if (s != PW_OK) break;
-        const double us = 1e3 * tmin / (double)total;
-        times.push_back(us);
         if (us < best) {
             best = us;
-            bestb = b;
+            best_sc = sc;
+        }
+    }
+    // stage 2: families per launch for that schedule (none below its group)
+    std::vector<int> cand;
+    std::vector<double> times;
+    int bestb = c->batch;
+    if (s == PW_OK) {
+        bool ok = true;
+        c->P = c->cmfma ? make_plan_bf16x2(c->n) : make_plan_sched(c->n, c->cdbl, best_sc, &ok);
+        const int bmin = first_pass_group(c->P, c->cdbl, c->batch);
+        for (int b = c->batch; b >= bmin && (int)cand.size() < 6; b /= 2) cand.push_back(b);
+        if (cand.empty()) cand.push_back(c->batch);
+        best = 1e300;
+        for (int b : cand) {
+            c->run_batch = b;
+            double us = 0.0;
+            s = time_it(&us);
+            if (s != PW_OK) break;
+            times.push_back(us);
+            if (us < best) {
+                best = us;
+                bestb = b;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->timing_every = saved_every;
     if (s != PW_OK) {
+        c->P = saved_P;
         c->run_batch = saved;
         return s;
     }
-    c->run_batch = bestb;
-    set_tuned_batch(c->device, c->n, prec_key(c, c->dtype), bestb);
+    tuned_put(c->device, c->n, prec_key(c, c->dtype), Tuned{best_sc, bestb, best});
+    // the tuned schedule takes effect unless the context asked for its own
+    c->P = saved_P;
+    apply_schedule(c, c->dtype);
     *best_batch = bestb;
     if (n_candidates) *n_candidates = (int)times.size();
     for (size_t i = 0; i < times.size(); ++i) {
         if (candidates) candidates[i] = cand[i];
         if (us_per_family) us_per_family[i] = times[i];
     }
+    return PW_OK;
+}
+
+pw_status pw_set_schedule(pw_ctx c, int first_bits, int column_tile_bits, int group, int batch) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if ((first_bits != 0 && first_bits != 12 && first_bits != 15) ||
+        (column_tile_bits != 0 && column_tile_bits != 12 && column_tile_bits != 13 && column_tile_bits != 15) ||
+        (group != 0 && group != 1 && group != 2 && group != 4 && group != 8) || batch < 0 || batch > MAX_BATCH)
+        return fail(PW_ERR_ARG, "schedule (%d, %d, %d, %d) outside the supported values", first_bits,
+                    column_tile_bits, group, batch);
+    const Schedule sc{first_bits, column_tile_bits, group};
+    if (c->bound && !c->cmfma) {
+        bool ok = true;
+        (void)make_plan_sched(c->n, c->cdbl, sc, &ok);
+        if (!ok)
+            return fail(PW_ERR_UNSUPPORTED, "schedule (%d, %d, %d) does not apply to n=%d", first_bits,
+                        column_tile_bits, group, c->n);
+    }
+    c->sched = sc;
+    c->sched_batch = batch;
+    if (c->bound) apply_schedule(c, c->dtype);
+    return PW_OK;
+}
+
+pw_status pw_get_schedule(pw_ctx c, int* first_bits, int* column_tile_bits, int* group, int* batch) {
+    pw_status s = check_state(c);
+    if (s != PW_OK) return s;
+    if (first_bits) *first_bits = c->P.fused ? 0 : c->P.k1;
+    if (column_tile_bits) *column_tile_bits = c->P.fused ? 0 : c->P.ktile;
+    if (group) *group = first_pass_group(c->P, c->cdbl, c->run_batch);
+    if (batch) *batch = c->run_batch;
+    return PW_OK;
+}
+
+pw_status pw_autotune_save(const char* path) {
+    if (!path) return fail(PW_ERR_ARG, "null path");
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(PW_ERR_ARG, "cannot write %s", path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    fprintf(f, "# pauliwht autotune v1: device-name n arithmetic first_bits column_tile_bits group batch us_per_family\n");
+    for (const auto& kv : g_tune) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, std::get<0>(kv.first)) != hipSuccess) continue;
+        const Tuned& t = kv.second;
+        fprintf(f, "%s %d %d %d %d %d %d %.6g\n", prop.gcnArchName, std::get<1>(kv.first), std::get<2>(kv.first),
+                t.sc.first_bits, t.sc.column_tile_bits, t.sc.group, t.batch, t.us);
+    }
+    fclose(f);
+    return PW_OK;
+}
+
+pw_status pw_autotune_load(const char* path, int* loaded) {
+    if (!path) return fail(PW_ERR_ARG, "null path");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(PW_ERR_ARG, "cannot read %s", path);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    std::vector<std::string> names;
+    for (int i = 0; i < ndev; ++i) {
+        hipDeviceProp_t prop;
+        names.push_back(hipGetDeviceProperties(&prop, i) == hipSuccess ? std::string(prop.gcnArchName) : "");
+    }
+    char line[512];
+    int cnt = 0;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        char name[256];
+        int n, key, fb, ct, g, b;
+        double us;
+        if (sscanf(line, "%255s %d %d %d %d %d %d %lf", name, &n, &key, &fb, &ct, &g, &b, &us) != 8) continue;
+        if (n < 1 || n > MAX_QUBITS || key < 0 || key > 2 || b < 0 || b > MAX_BATCH) continue;
+        for (int i = 0; i < ndev; ++i)
+            if (names[(size_t)i] == name) {
+                tuned_put(i, n, key, Tuned{Schedule{fb, ct, g}, b, us});
+                ++cnt;
+            }
+    }
+    fclose(f);
+    if (loaded) *loaded = cnt;
     return PW_OK;
 }
 
@@ -1659,13 +1834,15 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         c->cmfma = !c->cdbl && c->prec == PW_PREC_BF16X2;
         c->cpsi = c->psi;
         c->conv_valid = true;
-        c->P = c->cmfma ? make_plan_bf16x2(c->n) : make_plan(c->n, c->cdbl);
         const int B = Bk[(size_t)k];
         c->L = layout_for(c->n, c->dtype, B);
         if (c->L.total > cap) return fail(PW_ERR_WORKSPACE, "state %d does not fit the shared workspace", k);
         c->batch = B;
-        const int tuned = tuned_batch(c->device, c->n, c->cdbl ? 0 : c->cmfma ? 2 : 1);
-        c->run_batch = tuned > 0 && tuned < B ? tuned : B;
+        Tuned t{};
+        const bool have = tuned_get(c->device, c->n, c->cdbl ? 0 : c->cmfma ? 2 : 1, &t);
+        bool ok = true;
+        c->P = c->cmfma ? make_plan_bf16x2(c->n) : make_plan_sched(c->n, c->cdbl, have ? t.sc : Schedule{0, 0, 0}, &ok);
+        c->run_batch = have && t.batch > 0 && t.batch < B ? t.batch : B;
         c->cdf_valid = false;
         return PW_OK;
     };

@@ -58,7 +58,20 @@ struct Plan {
     // split-BF16 Hadamard blocks on the matrix cores for the single-workgroup transform and
     // the first pass (single precision storage; column passes stay FP32 on the VALU)
     bool mfma;
+    // families per first-pass tile-sharing group asked for by a schedule (0: the default
+    // policy of first_pass_group)
+    int grp_req;
 };
+
+// A transform schedule: first-pass bits (12, or 15 for single precision n - 1 = 16..27),
+// column-tile bits (12; 13 single precision; 15 single precision after a 15-bit first pass
+// with 9..12 bits left), first-pass group (1, 2, 4, 8); 0 = the default choice.
+struct Schedule {
+    int first_bits, column_tile_bits, group;
+};
+// The plan of a schedule; *honoured is false (and the default plan is returned) when the
+// schedule does not apply to (n, dbl).
+Plan make_plan_sched(int n, bool dbl, const Schedule& sc, bool* honoured);
 
 Plan make_plan(int n, bool dbl);
 // The plan of the split-BF16 matrix-core transform: single precision, the single-workgroup

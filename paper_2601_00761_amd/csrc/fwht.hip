@@ -1528,7 +1528,10 @@ void launch_first(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x
     const uint32_t tiles = 1u << (P.nh - TL - RL);
     const int grp = first_pass_group(P, sizeof(R) == 8, nb);
     const uint32_t blocks = tiles * (uint32_t)((nb + grp - 1) / grp * grp);
-    if (grp == 4)
+    if (grp == 8)
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 8>), dim3(blocks), dim3(1 << TL), st,
+                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+    else if (grp == 4)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 4>), dim3(blocks), dim3(1 << TL), st,
                   (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
     else if (grp == 2)
@@ -1645,6 +1648,70 @@ Plan make_plan_impl(int n, bool dbl, bool allow15);
 }
 
 Plan make_plan(int n, bool dbl) { return make_plan_impl(n, dbl, true); }
+
+Plan make_plan_sched(int n, bool dbl, const Schedule& sc, bool* honoured) {
+    Plan P = make_plan_impl(n, dbl, true);
+    bool ok = true;
+    if (sc.group != 0 && sc.group != 1 && sc.group != 2 && sc.group != 4 && sc.group != 8) ok = false;
+    if (!P.fused && ok && (sc.first_bits != 0 || sc.column_tile_bits != 0)) {
+        const int nh = n - 1;
+        int k1 = sc.first_bits ? sc.first_bits : P.k1;
+        if (k1 == 15) {
+            // 15-bit first pass, one column pass of s = n - 1 - 15 bits
+            const int sbits = nh - 15;
+            int kt = sc.column_tile_bits ? sc.column_tile_bits : (sbits <= 8 ? 12 : 15);
+            const bool fits = (kt == 12 && sbits <= 8) || (kt == 13 && sbits <= 9) || (kt == 15 && sbits >= 9);
+            if (dbl || sbits < 1 || sbits > 12 || !fits) {
+                ok = false;
+            } else {
+                P.k1 = 15;
+                P.npass = 1;
+                P.lo[0] = 15;
+                P.s[0] = sbits;
+                P.ktile = kt;
+                P.blocks_last = 1 << (nh - kt);
+            }
+        } else if (k1 == 12) {
+            const int kt = sc.column_tile_bits ? sc.column_tile_bits : (dbl ? 12 : 0);
+            if (kt != 0 && kt != 12 && !(kt == 13 && !dbl)) {
+                ok = false;
+            } else {
+                const Plan D = make_plan_impl(n, dbl, false);
+                P = D;
+                if (kt != 0 && kt != D.ktile) {
+                    // the other column tile: re-split the remaining bits for it
+                    const int smax = kt == 13 ? 9 : (dbl ? 9 : 8);
+                    const int rem = nh - K_FIRST;
+                    const int np = (rem + smax - 1) / smax;
+                    if (np > 4) {
+                        ok = false;
+                    } else {
+                        P.ktile = kt;
+                        P.npass = np;
+                        int lo = K_FIRST;
+                        for (int i = 0; i < np; ++i) {
+                            const int left = nh - lo;
+                            const int sb = (left + (np - i) - 1) / (np - i);
+                            P.lo[i] = lo;
+                            P.s[i] = sb;
+                            lo += sb;
+                        }
+                        P.blocks_last = 1 << (nh - kt);
+                    }
+                }
+            }
+        } else {
+            ok = false;
+        }
+    }
+    if (!ok) {
+        if (honoured) *honoured = false;
+        return make_plan_impl(n, dbl, true);
+    }
+    P.grp_req = P.fused ? 0 : sc.group;
+    if (honoured) *honoured = true;
+    return P;
+}
 
 Plan make_plan_bf16x2(int n) {
     Plan P = make_plan_impl(n, false, false);
@@ -1778,6 +1845,13 @@ hipError_t eval_reduced_batch(bool dbl, int max_alpha, const void* rho, int na, 
 }
 
 int first_pass_group(const Plan& P, bool dbl, int nb) {
+    if (P.grp_req > 0) {
+        // a schedule's group, within the launch and the numbering's need of 8 tiles
+        if (P.fused || P.mfma || P.nh - P.k1 < 3) return 1;
+        int g = 1;
+        while (g * 2 <= P.grp_req && g * 2 <= nb) g *= 2;
+        return g;
+    }
     // states of 16 MiB and more (measured: 4-21 % less time per family from 16 MiB to
     // 8 GiB); at least 8 tiles per family, which the grouped numbering needs
     if (P.fused || P.mfma || P.nh - P.k1 < 3 || ((size_t)(dbl ? 16 : 8) << P.n) < ((size_t)16 << 20)) return 1;

