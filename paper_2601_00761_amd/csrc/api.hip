@@ -136,9 +136,9 @@ int default_batch(int n, pw_dtype dt) {
     // power of two
     size_t p = 1;
     while (p * 2 <= b) p *= 2;
-    // states of 16 MiB and more: launches of at least four families, which the first
-    // pass runs in one tile-sharing group (up to 16 GiB of half spectra)
-    while (p < 4 && first_pass_group(P, dt == PW_C128, 4) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
+    // states of 16 MiB and more: launches of up to eight families, which the first pass
+    // runs in one tile-sharing group (up to 16 GiB of half spectra)
+    while (p < 8 && first_pass_group(P, dt == PW_C128, 8) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
     return (int)p;
 }
 
@@ -1522,7 +1522,7 @@ std::vector<Schedule> schedule_candidates(pw_ctx c) {
         const Plan P = make_plan_sched(c->n, c->cdbl, Schedule{pk.first, pk.second, 1}, &ok);
         if (!ok) continue;
         const bool can_group = P.nh - P.k1 >= 3;
-        for (int g : {1, 2, 4, 8}) {
+        for (int g : {1, 2, 4, 8, 16}) {
             if (g > 1 && (!can_group || g > c->batch)) continue;
             out.push_back(Schedule{pk.first, pk.second, g});
         }
@@ -1635,7 +1635,8 @@ pw_status pw_set_schedule(pw_ctx c, int first_bits, int column_tile_bits, int gr
     if (s != PW_OK) return s;
     if ((first_bits != 0 && first_bits != 12 && first_bits != 15) ||
         (column_tile_bits != 0 && column_tile_bits != 12 && column_tile_bits != 13 && column_tile_bits != 15) ||
-        (group != 0 && group != 1 && group != 2 && group != 4 && group != 8) || batch < 0 || batch > MAX_BATCH)
+        (group != 0 && group != 1 && group != 2 && group != 4 && group != 8 && group != 16) || batch < 0 ||
+        batch > MAX_BATCH)
         return fail(PW_ERR_ARG, "schedule (%d, %d, %d, %d) outside the supported values", first_bits,
                     column_tile_bits, group, batch);
     const Schedule sc{first_bits, column_tile_bits, group};

@@ -1528,7 +1528,10 @@ void launch_first(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x
     const uint32_t tiles = 1u << (P.nh - TL - RL);
     const int grp = first_pass_group(P, sizeof(R) == 8, nb);
     const uint32_t blocks = tiles * (uint32_t)((nb + grp - 1) / grp * grp);
-    if (grp == 8)
+    if (grp == 16)
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 16>), dim3(blocks), dim3(1 << TL), st,
+                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+    else if (grp == 8)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 8>), dim3(blocks), dim3(1 << TL), st,
                   (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
     else if (grp == 4)
@@ -1652,7 +1655,8 @@ Plan make_plan(int n, bool dbl) { return make_plan_impl(n, dbl, true); }
 Plan make_plan_sched(int n, bool dbl, const Schedule& sc, bool* honoured) {
     Plan P = make_plan_impl(n, dbl, true);
     bool ok = true;
-    if (sc.group != 0 && sc.group != 1 && sc.group != 2 && sc.group != 4 && sc.group != 8) ok = false;
+    if (sc.group != 0 && sc.group != 1 && sc.group != 2 && sc.group != 4 && sc.group != 8 && sc.group != 16)
+        ok = false;
     if (!P.fused && ok && (sc.first_bits != 0 || sc.column_tile_bits != 0)) {
         const int nh = n - 1;
         int k1 = sc.first_bits ? sc.first_bits : P.k1;
@@ -1855,7 +1859,9 @@ int first_pass_group(const Plan& P, bool dbl, int nb) {
     // states of 16 MiB and more (measured: 4-21 % less time per family from 16 MiB to
     // 8 GiB); at least 8 tiles per family, which the grouped numbering needs
     if (P.fused || P.mfma || P.nh - P.k1 < 3 || ((size_t)(dbl ? 16 : 8) << P.n) < ((size_t)16 << 20)) return 1;
-    return nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
+    // groups of eight (measured at n = 28 in launches of 64: 866 -> 807 us per family from
+    // four; n = 30: 4156 -> 4094 us)
+    return nb >= 8 ? 8 : nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
 }
 
 hipError_t sort_by_top_bit(const uint64_t* xs, int n, int nx, uint64_t* xs_sorted, uint32_t* perm, hipStream_t st) {

@@ -3,7 +3,7 @@
 Every plan variant that applies to a state (first pass over 12 or 15 index bits, column
 tiles of 12 / 13 / 15 bits) is checked against the FP64 oracle on the same input (single
 precision within the fp_bounds bound, double precision at 1e-10 relative, nullity counts
-exact), and the first-pass tile-sharing groups of 2, 4 and 8 families against group 1 of
+exact), and the first-pass tile-sharing groups of 2, 4, 8 and 16 families against group 1 of
 the same plan bitwise.  The autotuner's choice is one of the candidates, survives
 pw_autotune_save / pw_autotune_load, and reaches a new context.
 """
@@ -48,15 +48,15 @@ def test_every_schedule_matches_the_oracle(n, dtype):
     psi = synth.haar_state(n, 8000 + n)
     xs = _xs(n, 8100 + n)
     eps = 1e-7 if dtype == pw.PW_C128 else 1e-4
-    ctx = make_ctx(psi, dtype, x_batch=8)
+    ctx = make_ctx(psi, dtype, x_batch=16)
     r = oracle.eval_x_with_bound_sums(as_input(psi, dtype), xs, eps=eps, max_alpha=4)
     for fb, ct in _plans(n, dtype):
         base = None
-        for g in (1, 2, 4, 8):
-            pw.pw_set_schedule(ctx.h, fb, ct, g, 8)
+        for g in (1, 2, 4, 8, 16):
+            pw.pw_set_schedule(ctx.h, fb, ct, g, 16)
             got = pw.pw_get_schedule(ctx.h)
             log("schedule n=%d dtype=%d first=%d column=%d group=%d -> %s" % (n, dtype, fb, ct, g, got))
-            assert got[:2] == (fb, ct) and got[3] == 8
+            assert got[:2] == (fb, ct) and got[3] == 16
             assert got[2] == g or (g > 1 and got[2] < g)
             res = ctx.eval_x(xs, eps)
             if base is None:
