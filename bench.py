@@ -373,13 +373,15 @@ LEARNED_N = 30
 
 
 def learned_leg(pw, torch, stream, kind, draws, pilot):
-    """Learned (MADE) proposal against the plain exact-marginal sampler at N = 30, complex64,
-    the same number of draws each (x = 0 evaluated in both).  kind "psi_m": |T>^15 |0>^15
-    (exact M_2 = 15 log2(4/3)); kind "tdoped": |0...0> through a T-doped brick-wall stream
-    (eta = 8, N_T = 60).  The learned run trains a 30 -> 256 -> 256 -> 30 MADE on `pilot`
-    exact-marginal draws (weights m_2/p) and samples the defensive mixture with lambda = 0.1.
-    Reported: M_2 +- sigma, draws, wall times, and the draws sigma = 1e-3 would need
-    (n sigma^2 / 1e-6) for each."""
+    """Learned (MADE) proposal against plain sampling at N = 30, complex64, the same number of
+    draws each (x = 0 evaluated in both).  kind "psi_m": |T>^15 |0>^15 (exact M_2 =
+    15 log2(4/3)); kind "tdoped": |0...0> through a T-doped brick-wall stream (eta = 8,
+    N_T = 60).  Plain: pw_mc_auto (the sampler with the smaller pilot spread).  Learned:
+    pw_mc_learned_auto -- a 30 -> 256 -> 256 -> 30 MADE trained on three quarters of `pilot`
+    exact-marginal draws (weights m_2/p), the defensive component chosen from the pilot, and
+    plain sampling kept when the held-out quarter predicts it spreads less than the mixture.
+    Reported: M_2 +- sigma, the draws and the projected wall time sigma = 1e-3 would need
+    for each (draws: n sigma^2 / 1e-6, at the measured cost per draw, plus fixed costs)."""
     import numpy as np
     import synth
     n = LEARNED_N
@@ -403,29 +405,39 @@ def learned_leg(pw, torch, stream, kind, draws, pilot):
         ctx.apply_gates(*synth.gates_to_arrays(synth.tdoped_stream(n, 8, 2 * n, seed)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 64, draws + 1, 0.0, seed + 1)
+    plain, pchosen, pr2 = pw.pw_mc_auto(ctx.h, 1e-4, 64, draws + 1, 0.0, seed + 1, 512)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hidden = 256
     pw.pw_made_init(ctx.h, n, hidden, synth.made_init(n, hidden, seed + 2))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    learned = pw.pw_mc_learned(ctx.h, 1e-4, 64, draws + 1, 0.0, seed + 3, 0.1, pilot, 20, 128, 3e-3)
+    learned, lchosen, pred = pw.pw_mc_learned_auto(ctx.h, 1e-4, 64, draws + 1, 0.0, seed + 3, 0.1, pilot, 20, 128,
+                                                   3e-3)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     ctx.close()
     del psi
+    per_draw = (t1 - t0) / (plain["n_samples"] + 512)
 
-    def leg(r, wall):
+    def leg(r, wall, fixed):
         se = r["M_se"][0]
         need = r["n_samples"] * (se / 1e-3) ** 2
         return {"M2": r["M"][0], "M2_se": se, "r2": r["r"][0], "n_samples": r["n_samples"], "wall_s": wall,
-                "samples_for_se_1e-3": need}
+                "samples_for_se_1e-3": need, "projected_wall_s_for_se_1e-3": fixed + need * per_draw}
+    names = {0: "uniform", 1: "exact marginal", 2: "mixture, uniform defensive", 3: "mixture, marginal defensive"}
+    lfixed = max(0.0, (t3 - t2) - learned["n_samples"] * per_draw)
     out = {"workload": ("N=30 psi_m = |T>^15 |0>^15, complex64" if kind == "psi_m" else
                         "N=30 T-doped Clifford state, eta=8, N_T=60, complex64, no preconditioning"),
-           "draws_each": draws, "plain_marginal": leg(plain, t1 - t0),
-           "learned": dict(leg(learned, t3 - t2), pilot=pilot, hidden=hidden, lam=0.1, epochs=20, minibatch=128,
-                           lr=3e-3, note="wall time includes the pilot draws and the training")}
+           "draws_each": draws, "cost_per_draw_s": per_draw,
+           "plain": dict(leg(plain, t1 - t0, 512 * per_draw), sampler=names[pchosen],
+                         pilot_r2={"uniform": pr2[0], "marginal": pr2[1]}),
+           "learned": dict(leg(learned, t3 - t2, lfixed), chosen=names[lchosen],
+                           held_out_predicted_r2={"uniform": pred[0], "marginal": pred[1], "mixture": pred[2]},
+                           pilot=pilot, hidden=hidden, lam=0.1, epochs=20, minibatch=128, lr=3e-3,
+                           note="wall time includes the pilot draws and the training (fixed cost %.1f s)" % lfixed)}
+    out["learned_faster_to_se_1e-3"] = bool(out["learned"]["projected_wall_s_for_se_1e-3"] <
+                                            out["plain"]["projected_wall_s_for_se_1e-3"])
     if exact is not None:
         out["M2_exact"] = exact
     return out
@@ -672,8 +684,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learned-draws", type=int, default=1024)
     ap.add_argument("--learned-pilot", type=int, default=2048)
-    ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=["tdoped"],
-                    help="N=30 learned-vs-plain proposal comparison (default: the T-doped state of the workload)")
+    ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=["tdoped", "psi_m"],
+                    help="N=30 learned-vs-plain proposal comparison (the T-doped state of the workload, and psi_m)")
     ap.add_argument("--no-learned-leg", action="store_true")
     ap.add_argument("--mc-eta", type=int, nargs="*", default=[],
                     help="extra N=28 Monte Carlo legs (marginal sampler, 16384 families) at these eta")

@@ -278,14 +278,27 @@ PW_API pw_status pw_made_train(pw_ctx ctx, const uint64_t* xs, const double* w, 
 PW_API pw_status pw_made_sample(pw_ctx ctx, uint64_t seed, uint64_t offset, int64_t count, uint64_t* xs_out);
 /* Monte Carlo with the learned proposal: x = 0 evaluated; `pilot` draws from the exact
  * marginal are evaluated and the network is trained on them with weights m_{2;x}/p(x)
- * (targets the zero-variance proposal t(x) ~ m_{2;x}); then draws from the defensive
- * mixture q = lambda p(.|x!=0) + (1-lambda) q_theta(.|x!=0) (per-sample choice from
- * Philox stream "MIXC") are weighted exactly by m_{alpha;x}/q(x), until the standard
- * error of M_2 is <= target_se or max_samples families (x = 0 included; pilot
- * families not counted). */
+ * (targets the zero-variance proposal t(x) ~ m_{2;x}); the same pilot estimates the spread
+ * of the two plain samplers (as in pw_mc_auto) and the one that spreads less becomes the
+ * defensive component q_def (uniform over x != 0, or the exact marginal p(.|x!=0)); then
+ * draws from the mixture q = lambda q_def + (1-lambda) q_theta(.|x!=0) (per-sample choice
+ * from Philox stream "MIXC") are weighted exactly by m_{alpha;x}/q(x), until the standard
+ * error of M_2 is <= target_se or max_samples families (x = 0 included; pilot families not
+ * counted). */
 PW_API pw_status pw_mc_learned(pw_ctx ctx, double eps, int batch, uint64_t max_samples, double target_se,
                                uint64_t seed, double lambda, int64_t pilot, int epochs, int minibatch, double lr,
                                pw_result* out);
+
+/* pw_mc_learned with plain sampling kept as the judge: the network trains on the first
+ * three quarters of the pilot, and on the held-out quarter the second moment of m/g is
+ * estimated for g = uniform, exact marginal and the mixture (E_{p_c}[m^2 / (g p_c)], p_c the
+ * marginal on x != 0).  If a plain sampler is predicted to spread less than the mixture,
+ * that sampler runs (pw_mc on the stream seed + 0x9E3779B97F4A7C15) instead.  *chosen: 0
+ * uniform, 1 marginal, 2 mixture with the uniform, 3 mixture with the marginal;
+ * predicted_r2[3]: the held-out r_2 of uniform, marginal and mixture.  pilot >= 8. */
+PW_API pw_status pw_mc_learned_auto(pw_ctx ctx, double eps, int batch, uint64_t max_samples, double target_se,
+                                    uint64_t seed, double lambda, int64_t pilot, int epochs, int minibatch,
+                                    double lr, int* chosen, double* predicted_r2, pw_result* out);
 
 /* Stabilizer Renyi entropy of the reduced state rho_A on the first n_a qubits
  * (Supplemental Material, mixed states, Eq. Msre-mixed):

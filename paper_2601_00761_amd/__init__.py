@@ -23,7 +23,7 @@ __all__ = [
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
     "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_eval_x_noalloc", "pw_family_values",
     "pw_sample_x", "pw_exact", "pw_mc", "pw_mc_auto", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_set_schedule", "pw_get_schedule", "pw_autotune_save", "pw_autotune_load", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
-    "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
+    "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_mc_learned_auto", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
 
@@ -141,6 +141,8 @@ def _load():
         "pw_made_sample": ([_vp, _u64, _u64, _i64, _vp], _int),
         "pw_mc_learned": ([_vp, _dbl, _int, _u64, _dbl, _u64, _dbl, _i64, _int, _int, _dbl,
                            ctypes.POINTER(pw_result)], _int),
+        "pw_mc_learned_auto": ([_vp, _dbl, _int, _u64, _dbl, _u64, _dbl, _i64, _int, _int, _dbl,
+                                ctypes.POINTER(_int), ctypes.POINTER(_dbl), ctypes.POINTER(pw_result)], _int),
         "pw_timing_enable": ([_vp, _int], _int),
         "pw_timing_read": ([_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(_dbl), ctypes.POINTER(_u64)], _int),
         "pw_timing_reset": ([_vp], _int),
@@ -435,6 +437,18 @@ def pw_mc_learned(ctx, eps, batch, max_samples, target_se, seed, lam, pilot, epo
     _check(_L.pw_mc_learned(ctx, float(eps), int(batch), int(max_samples), float(target_se), int(seed), float(lam),
                             int(pilot), int(epochs), int(minibatch), float(lr), ctypes.byref(r)))
     return r.as_dict()
+
+
+def pw_mc_learned_auto(ctx, eps, batch, max_samples, target_se, seed, lam, pilot, epochs, minibatch, lr):
+    """(result dict, chosen: 0 uniform / 1 marginal / 2 mixture+uniform / 3 mixture+marginal,
+    held-out predicted r_2 of (uniform, marginal, mixture))."""
+    r = pw_result()
+    ch = _int()
+    pr = (_dbl * 3)()
+    _check(_L.pw_mc_learned_auto(ctx, float(eps), int(batch), int(max_samples), float(target_se), int(seed), float(lam),
+                                 int(pilot), int(epochs), int(minibatch), float(lr), ctypes.byref(ch), pr,
+                                 ctypes.byref(r)))
+    return r.as_dict(), ch.value, tuple(pr)
 
 
 def pw_timing_enable(ctx, every):

@@ -1326,8 +1326,16 @@ pw_status pw_made_sample(pw_ctx c, uint64_t seed, uint64_t offset, int64_t count
     return PW_OK;
 }
 
-pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, double target_se, uint64_t seed,
-                        double lambda, int64_t pilot, int epochs, int minibatch, double lr, pw_result* out) {
+namespace {
+// Monte Carlo with the learned proposal (see pw_mc_learned).  mode: 0 = defensive mixture
+// with the defensive component chosen from the pilot; 1 = the same, but when a held-out
+// quarter of the pilot predicts that plain sampling (uniform or marginal) spreads less
+// than the mixture, that sampler runs instead.  *chosen: 0 uniform, 1 marginal, 2 mixture
+// with the uniform, 3 mixture with the marginal; pred[3]: predicted r_2 of uniform,
+// marginal and mixture (held-out quarter; NaN where not computed).
+pw_status mc_learned_core(pw_ctx c, double eps, int batch, uint64_t max_samples, double target_se, uint64_t seed,
+                          double lambda, int64_t pilot, int epochs, int minibatch, double lr, int mode, int* chosen,
+                          double* pred, pw_result* out) {
     pw_status s = check_state(c);
     if (s != PW_OK) return s;
     s = made_check(c);
@@ -1336,9 +1344,10 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
     if (c->made.D.n != c->n) return fail(PW_ERR_ARG, "learned proposal has n=%d, state has n=%d", c->made.D.n, c->n);
     if (!(lambda > 0.0 && lambda <= 1.0)) return fail(PW_ERR_ARG, "lambda must be in (0, 1]");
     if (batch < 1 || batch > c->made.maxB) return fail(PW_ERR_ARG, "batch must be in [1, %d]", c->made.maxB);
-    if (pilot < 1 || max_samples < 3) return fail(PW_ERR_ARG, "need pilot >= 1 and max_samples >= 3");
+    if (pilot < 8 || max_samples < 3) return fail(PW_ERR_ARG, "need pilot >= 8 and max_samples >= 3");
     if (!(eps >= 0.0 && eps < 1.0)) return fail(PW_ERR_ARG, "eps=%g outside [0, 1)", eps);
     const int n = c->n;
+    const double d = ldexp(1.0, n);
     FamilyRes r0;
     const uint64_t zero = 0;
     s = eval_host(c, &zero, 1, eps, &r0);
@@ -1354,15 +1363,60 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
         if (px[i] == 0) return fail(PW_ERR_UNSUPPORTED, "the marginal sampler drew x = 0 (|psi|^2 is a point mass)");
     s = eval_host(c, px.data(), pilot, eps, pr.data());
     if (s != PW_OK) return s;
-    std::vector<double> pw_((size_t)pilot);
-    for (int64_t i = 0; i < pilot; ++i) pw_[i] = pr[i].m[0] / pr[i].p;
-    s = pw_made_train(c, px.data(), pw_.data(), pilot, epochs, minibatch, lr, seed ^ 0x5EEDull, nullptr);
+    // the defensive component: the plain sampler with the smaller spread on the pilot
+    std::vector<DrawMP> dm((size_t)pilot);
+    for (int64_t i = 0; i < pilot; ++i) dm[(size_t)i] = {pr[i].m[0], pr[i].p};
+    const Spreads sp = spreads_from_marginal_pilot(dm, r0.m[0], p0, d);
+    const bool def_uniform = sp.r_uniform < sp.r_marginal;
+    // train on the first three quarters (all of the pilot in mode 0)
+    const int64_t ntrain = mode == 1 ? pilot - pilot / 4 : pilot;
+    std::vector<double> pw_((size_t)ntrain);
+    for (int64_t i = 0; i < ntrain; ++i) pw_[i] = pr[i].m[0] / pr[i].p;
+    s = pw_made_train(c, px.data(), pw_.data(), ntrain, epochs, minibatch, lr, seed ^ 0x5EEDull, nullptr);
     if (s != PW_OK) return s;
     double lq0 = 0.0;
     s = made_logq_host(c, &zero, 1, &lq0);
     if (s != PW_OK) return s;
     const double q0 = exp(lq0);
-    // defensive mixture q = lambda p(.|x!=0) + (1 - lambda) q_theta(.|x!=0), exact weights m / q
+    // proposal density on x != 0 of the mixture
+    auto qmix = [&](double p, double lqx) {
+        const double qd = def_uniform ? 1.0 / (d - 1.0) : p / (1.0 - p0);
+        return lambda * qd + (1.0 - lambda) * exp(lqx) / (1.0 - q0);
+    };
+    int pick = def_uniform ? 2 : 3;
+    double pr3[3] = {NAN, NAN, NAN};
+    if (mode == 1) {
+        // held-out quarter, x ~ p_c = p / (1 - p0): the second moment of m / g under a
+        // proposal g is E_{p_c}[m^2 / (g p_c)]; its mean is S - m_0 for every g
+        const int64_t h0 = ntrain, nh = pilot - ntrain;
+        std::vector<double> lqh((size_t)nh);
+        s = made_logq_host(c, px.data() + h0, nh, lqh.data());
+        if (s != PW_OK) return s;
+        double mu = 0.0, su = 0.0, sm = 0.0, sx = 0.0;
+        for (int64_t i = 0; i < nh; ++i) {
+            const double m = pr[h0 + i].m[0], p = pr[h0 + i].p, pc = p / (1.0 - p0);
+            mu += m / pc;
+            su += m * m * (d - 1.0) / pc;           // g = 1 / (d - 1)
+            sm += m * m / (pc * pc);                // g = p_c
+            sx += m * m / (qmix(p, lqh[i]) * pc);   // g = the mixture
+        }
+        mu /= (double)nh;
+        const double S = r0.m[0] + mu;
+        auto rr = [&](double second) { return sqrt(fmax(second / (double)nh - mu * mu, 0.0)) / S; };
+        pr3[0] = rr(su);
+        pr3[1] = rr(sm);
+        pr3[2] = rr(sx);
+        if (pr3[0] < pr3[2] || pr3[1] < pr3[2]) pick = pr3[0] < pr3[1] ? 0 : 1;
+    }
+    if (chosen) *chosen = pick;
+    if (pred)
+        for (int k = 0; k < 3; ++k) pred[k] = pr3[k];
+    if (pick < 2) {
+        // plain sampling judged better: the estimator of pw_mc on a stream of its own
+        return pw_mc(c, pick == 0 ? PW_SAMPLER_UNIFORM_NZ : PW_SAMPLER_MARGINAL_NZ, eps, batch, max_samples,
+                     target_se, seed + 0x9E3779B97F4A7C15ull, out);
+    }
+    // defensive mixture q = lambda q_def + (1 - lambda) q_theta(.|x != 0), exact weights m / q
     Running run[4];
     double gap = r0.gap;
     uint64_t drawn = 0;
@@ -1379,7 +1433,7 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
         xs.resize((size_t)nb);
         res.resize((size_t)nb);
         lq.resize((size_t)nb);
-        s = pw_sample_x(c, PW_SAMPLER_MARGINAL_NZ, seed_mc, drawn, nb, xm.data());
+        s = pw_sample_x(c, def_uniform ? PW_SAMPLER_UNIFORM_NZ : PW_SAMPLER_MARGINAL_NZ, seed_mc, drawn, nb, xm.data());
         if (s != PW_OK) return s;
         s = pw_made_sample(c, seed_mc, drawn, nb, xl.data());
         if (s != PW_OK) return s;
@@ -1396,8 +1450,7 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
         if (s != PW_OK) return s;
         for (int64_t i = 0; i < nb; ++i) {
             const FamilyRes& f = res[i];
-            const double q = lambda * f.p / (1.0 - p0) + (1.0 - lambda) * exp(lq[i]) / (1.0 - q0);
-            const double wgt = 1.0 / q;
+            const double wgt = 1.0 / qmix(f.p, lq[i]);
             for (int a = 0; a < 3; ++a) run[a].add(wgt * f.m[a]);
             run[3].add(wgt * f.ent);
             gap = fmax(gap, f.gap);
@@ -1421,14 +1474,28 @@ pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, d
     }
     r.L = r0.ent + run[3].mean;
     r.L_se = sqrt(run[3].var() / run[3].n);
-    r.M1 = -r.L / ldexp(1.0, n);
-    r.M1_se = r.L_se / ldexp(1.0, n);
+    r.M1 = -r.L / d;
+    r.M1_se = r.L_se / d;
     r.P = NAN;
     r.nullity = NAN;
     r.n_samples = drawn + 1;
     r.gap = gap;
     *out = r;
     return PW_OK;
+}
+}  // namespace
+
+pw_status pw_mc_learned(pw_ctx c, double eps, int batch, uint64_t max_samples, double target_se, uint64_t seed,
+                        double lambda, int64_t pilot, int epochs, int minibatch, double lr, pw_result* out) {
+    return mc_learned_core(c, eps, batch, max_samples, target_se, seed, lambda, pilot, epochs, minibatch, lr, 0,
+                           nullptr, nullptr, out);
+}
+
+pw_status pw_mc_learned_auto(pw_ctx c, double eps, int batch, uint64_t max_samples, double target_se, uint64_t seed,
+                             double lambda, int64_t pilot, int epochs, int minibatch, double lr, int* chosen,
+                             double* predicted_r2, pw_result* out) {
+    return mc_learned_core(c, eps, batch, max_samples, target_se, seed, lambda, pilot, epochs, minibatch, lr, 1,
+                           chosen, predicted_r2, out);
 }
 
 pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {

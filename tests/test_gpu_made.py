@@ -6,6 +6,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from gpu_util import log, make_ctx
 from oracle import made
@@ -63,6 +64,59 @@ def test_one_adam_step_matches_reference():
     big = np.abs(g) > 1e-5
     assert np.max(np.abs(got[big] - ref[big])) < 1e-6
     assert np.max(np.abs(got - ref)) < 1e-2 + 1e-6
+
+
+def test_three_adam_steps_match_reference():
+    # full-batch training for three epochs = three Adam steps (bias corrections at t = 2, 3
+    # and the moment recursions, pinned in test_oracle_made.py against a hand-worked
+    # recursion), against the FP64 reference stepping with its own gradients
+    n, h = 8, 64
+    p = f32(synth.made_init(n, h, 33))
+    xs = synth.splitmix64(9, 0, 64) % np.uint64(1 << n)
+    w = 0.5 + (synth.splitmix64(10, 0, 64) % np.uint64(100)).astype(float) / 100.0
+    ctx = pw.Context(0)
+    pw.pw_made_init(ctx.h, n, h, p)
+    pw.pw_made_train(ctx.h, xs, w, 3, 64, 1e-2, 0)
+    got = pw.pw_made_get(ctx.h, n, h)
+    ctx.close()
+    ref = p.copy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    gmin = np.full_like(p, np.inf)
+    for t in (1, 2, 3):
+        _, g = made.loss_and_grad(ref, n, h, xs, w)
+        gmin = np.minimum(gmin, np.abs(g))
+        ref, m, v = made.adam_step(ref, g, m, v, t, 1e-2)
+    # coordinates whose gradient stays well above FP32 noise in every step are determined
+    big = gmin > 1e-4
+    assert big.sum() > 100
+    assert np.max(np.abs(got[big] - ref[big])) < 2e-5
+    assert np.max(np.abs(got - ref)) < 3e-2 + 1e-6
+
+
+def test_learned_auto_keeps_plain_sampling_as_the_judge():
+    # psi_m: the mixture is predicted (held-out quarter) and found to spread far less than
+    # plain sampling; a Haar state: whatever is chosen is the smallest prediction, and a
+    # plain choice is bitwise pw_mc on the documented stream
+    n, h = 14, 128
+    for kind in ("psi_m", "haar"):
+        psi = synth.psi_m_state(n) if kind == "psi_m" else synth.haar_state(n, 6400)
+        ctx = make_ctx(psi, pw.PW_C128)
+        pw.pw_made_init(ctx.h, n, h, synth.made_init(n, h, 65))
+        res, chosen, pred = pw.pw_mc_learned_auto(ctx.h, 1e-7, 64, 1025, 0.0, 21, 0.1, 1024, 30, 128, 3e-3)
+        log("learned auto %s: chosen %d predicted r2 %s, M2 %.5f +- %.5f" % (kind, chosen, pred, res["M"][0],
+                                                                          res["M_se"][0]))
+        exact = oracle.alg1(psi, max_alpha=2)["M"][2]
+        assert abs(res["M"][0] - exact) < 5 * res["M_se"][0] + 1e-9
+        if chosen < 2:
+            assert pred[chosen] <= pred[2] and pred[chosen] <= pred[1 - chosen]
+            ref = ctx.mc(chosen, 1e-7, 64, 1025, 0.0, 21 + 0x9E3779B97F4A7C15)
+            assert np.array_equal(np.asarray(res["M"]), np.asarray(ref["M"]))
+        else:
+            assert pred[2] <= min(pred[0], pred[1])
+        if kind == "psi_m":
+            assert chosen == 3 and pred[2] < 0.5 * pred[1]
+        ctx.close()
 
 
 def test_sampler_matches_reference():
