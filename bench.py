@@ -443,6 +443,14 @@ def learned_leg(pw, torch, stream, kind, draws, pilot):
     return out
 
 
+T0 = time.perf_counter()
+
+
+def note(msg):
+    """A progress line on stderr (the JSON result is the only line on stdout)."""
+    print("[bench %6.1f s] %s" % (time.perf_counter() - T0, msg), file=sys.stderr, flush=True)
+
+
 HEAD_N = 28
 HEAD_BATCH = 64           # families per launch (a lent workspace of 64 families)
 HEAD_FAMILIES = 2048      # drawn families per step
@@ -494,6 +502,7 @@ def headline_steps(pw, torch, ctx, seed, steps, warmup):
     pw.pw_set_graphs(ctx.h, 0)
     for w in range(warmup):
         ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, HEAD_BATCH, HEAD_FAMILIES + 1, 0.0, seed + 1000 + w)
+        note("headline warm-up step %d/%d" % (w + 1, warmup))
     pw.pw_timing_enable(ctx.h, 1)
     pw.pw_timing_reset(ctx.h)
     torch.cuda.synchronize()
@@ -503,6 +512,8 @@ def headline_steps(pw, torch, ctx, seed, steps, warmup):
     for k in range(steps):
         last = ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, HEAD_BATCH, HEAD_FAMILIES + 1, 0.0, seed + 2000 + k)
         fams += last["n_samples"]
+        if (k + 1) % 5 == 0 or k + 1 == steps:
+            note("headline step %d/%d" % (k + 1, steps))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     kt = {}
@@ -585,6 +596,9 @@ def sigma_leg(pw, torch, ctx, seed, budget_s, per_family_s, precondition_s):
     steps replayed as HIP graphs, at most as many families as budget_s allows at the measured
     cost per family."""
     cap = max(4096, int(budget_s / per_family_s))
+    note("sigma leg: up to %d families (%.0f s budget)" % (cap, budget_s))
+    pw.pw_set_progress(ctx.h, lambda fam, m2, se: note("sigma leg: %d families, M2 %.5f +- %.5f" % (fam, m2, se)),
+                       20.0)
     pw.pw_set_graphs(ctx.h, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -592,6 +606,7 @@ def sigma_leg(pw, torch, ctx, seed, budget_s, per_family_s, precondition_s):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     pw.pw_set_graphs(ctx.h, 0)
+    pw.pw_set_progress(ctx.h, None)
     se = res["M_se"][0]
     return {"workload": "M_2 of the headline state (N=%d, complex64, preconditioned) to std-err %g; exact-marginal pilot of 2048 "
                         "draws, the sampler with the smaller spread then runs to the target or the family cap"
@@ -673,19 +688,22 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--eta", type=int, default=16, help="scrambling ratio of the headline state (workload: 1, 4, 16)")
-    ap.add_argument("--sigma-budget", type=float, default=240.0,
+    ap.add_argument("--sigma-budget", type=float, default=480.0,
                     help="wall seconds the M_2-to-1e-3 leg may spend sampling (0: skip it)")
-    ap.add_argument("--total-budget", type=float, default=540.0,
+    ap.add_argument("--total-budget", type=float, default=565.0,
                     help="the sigma leg is shortened so that the whole run stays within this many seconds")
+    ap.add_argument("--only-n20", action="store_true",
+                    help="run only the N=20 exact-enumeration legs and print them (profiling; not a benchmark line)")
     ap.add_argument("--sweep-steps", type=int, default=2, help="timed N=20 exact sweeps in complex64 (0: skip)")
     ap.add_argument("--steps-c128", type=int, default=1)
     ap.add_argument("--timing-every", type=int, default=16, help="N=20 leg: time every k-th launch of each class")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learned-draws", type=int, default=1024)
     ap.add_argument("--learned-pilot", type=int, default=2048)
-    ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=["tdoped", "psi_m"],
-                    help="N=30 learned-vs-plain proposal comparison (the T-doped state of the workload, and psi_m)")
+    ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=["tdoped"],
+                    help="N=30 learned-vs-plain proposal comparison (default: the T-doped state of the workload; "
+                         "psi_m shows the learnable case)")
     ap.add_argument("--no-learned-leg", action="store_true")
     ap.add_argument("--mc-eta", type=int, nargs="*", default=[],
                     help="extra N=28 Monte Carlo legs (marginal sampler, 16384 families) at these eta")
@@ -706,12 +724,18 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    t_start = time.perf_counter()
+    t_start = T0
     import torch
     import paper_2601_00761_amd as pw
 
+    note("torch and the library loaded")
     stream = torch.cuda.current_stream(0)
+    if args.only_n20:
+        print(json.dumps(sweep20_leg(pw, torch, stream, max(args.sweep_steps, 1), 1, args.steps_c128,
+                                     args.timing_every, args.max_alpha)), flush=True)
+        return
     ctx, seed, pre_s = headline_state(pw, torch, stream, args.eta)
+    note("headline state prepared and preconditioned")
     el, fams, last, kt = headline_steps(pw, torch, ctx, seed, args.steps, args.warmup)
     strings = float(1 << HEAD_N)
     value = fams * strings / el
@@ -742,11 +766,14 @@ def main():
     }
     per_family_s = el / fams
     if not args.no_cpu_baseline:
+        note("cpu baseline")
         out["cpu_baseline"] = headline_cpu_baseline(pw, ctx, seed, args.cpu_budget)
     if args.sweep_steps > 0:
+        note("N=20 exact enumeration legs")
         out["n20_exact"] = sweep20_leg(pw, torch, stream, args.sweep_steps, 1, args.steps_c128, args.timing_every,
                                        args.max_alpha)
     if not args.no_learned_leg and args.learned_leg:
+        note("N=30 learned-vs-plain legs")
         out["learned_vs_plain"] = [learned_leg(pw, torch, stream, k, args.learned_draws, args.learned_pilot)
                                    for k in args.learned_leg]
     for eta in args.mc_eta:

@@ -138,7 +138,7 @@ PW_API pw_status pw_workspace_size(int n_qubits, pw_dtype dtype, int x_batch, si
  * its scratch from it.  Pass NULL/0 to return to library-owned scratch.  A lent
  * buffer runs the largest launch it holds.  Library-owned scratch is sized for
  * the default launch: up to 256 MiB of half spectra (at most 256 families), and
- * up to eight families (within 16 GiB) for states of 16 MiB and more, whose
+ * up to sixteen families (within 16 GiB) for states of 16 MiB and more, whose
  * first pass runs them in one group sharing the state's tiles; lists are
  * then evaluated in order of the top bit of x and the results put back in list
  * order. */
@@ -385,6 +385,13 @@ PW_API pw_status pw_eval_states(pw_ctx ctx, int nstates, const pw_state_ref* sta
  * kernel runs.  Use a nullity tolerance of at least 1e-4 with PW_PREC_F32 or BF16X2; a
  * nullity count that is not a power of two still returns PW_ERR_TOLERANCE from pw_exact. */
 PW_API pw_status pw_set_precision(pw_ctx ctx, pw_prec prec);
+
+/* Progress of long Monte Carlo estimates (pw_mc, pw_mc_auto and the plain fallback of
+ * pw_mc_learned_auto): after a sampling step, at most once per every_seconds of wall time,
+ * fn(user, families evaluated so far (x = 0 included), current M_2, its standard error) is
+ * called on the calling thread.  fn = NULL switches it off (the default). */
+typedef void (*pw_progress_fn)(void* user, uint64_t families, double M2, double M2_se);
+PW_API pw_status pw_set_progress(pw_ctx ctx, pw_progress_fn fn, void* user, double every_seconds);
 
 /* Test support for the error paths: every later HIP call of one class made by this
  * context fails before it is issued (fault_class 1 = device or pinned allocation, 2 =

@@ -22,7 +22,7 @@ __all__ = [
     "pw_version", "pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_workspace_size", "pw_set_workspace",
     "pw_state_bind", "pw_state_upload", "pw_apply_gates", "pw_precondition", "pw_precondition_circuit",
     "pw_clifford2_table", "pw_eval_x", "pw_eval_x_device", "pw_eval_x_noalloc", "pw_family_values",
-    "pw_sample_x", "pw_exact", "pw_mc", "pw_mc_auto", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_autotune", "pw_set_schedule", "pw_get_schedule", "pw_autotune_save", "pw_autotune_load", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
+    "pw_sample_x", "pw_exact", "pw_mc", "pw_mc_auto", "pw_set_moments", "pw_set_graphs", "pw_inject_fault", "pw_set_progress", "pw_autotune", "pw_set_schedule", "pw_get_schedule", "pw_autotune_save", "pw_autotune_load", "pw_eval_states", "pw_mixed", "pw_made_param_count", "pw_made_init", "pw_made_get", "pw_made_logq",
     "pw_made_grad", "pw_made_train", "pw_made_sample", "pw_mc_learned", "pw_mc_learned_auto", "pw_timing_enable", "pw_timing_read", "pw_timing_reset", "lib_path",
     "Context",
 ]
@@ -123,6 +123,7 @@ def _load():
                         ctypes.POINTER(pw_result)], _int),
         "pw_set_graphs": ([_vp, _int], _int),
         "pw_inject_fault": ([_vp, _int], _int),
+        "pw_set_progress": ([_vp, _vp, _vp, _dbl], _int),
         "pw_set_precision": ([_vp, _int], _int),
         "pw_set_schedule": ([_vp, _int, _int, _int, _int], _int),
         "pw_get_schedule": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
@@ -361,6 +362,22 @@ def pw_eval_states(ctx, states, state_idx, xs, eps):
 def pw_set_precision(ctx, prec):
     """Arithmetic of later family evaluations (PW_PREC_AUTO, _F64, _F32, _BF16X2)."""
     _check(_L.pw_set_precision(ctx, int(prec)))
+
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_double)
+_progress_keep = {}
+
+
+def pw_set_progress(ctx, fn, every_seconds=10.0):
+    """fn(families, M2, M2_se) after Monte Carlo steps, at most every every_seconds; None clears."""
+    key = ctx.value if hasattr(ctx, "value") else int(ctx)
+    if fn is None:
+        _progress_keep.pop(key, None)
+        _check(_L.pw_set_progress(ctx, None, None, 0.0))
+        return
+    cb = PROGRESS_FN(lambda user, fam, m2, se: fn(int(fam), float(m2), float(se)))
+    _progress_keep[key] = cb   # the C side holds the pointer: keep the thunk alive
+    _check(_L.pw_set_progress(ctx, ctypes.cast(cb, ctypes.c_void_p), None, float(every_seconds)))
 
 
 FAULT_CLASSES = {None: 0, "alloc": 1, "launch": 2, "copy": 3}

@@ -11,6 +11,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <string>
@@ -136,9 +137,9 @@ int default_batch(int n, pw_dtype dt) {
     // power of two
     size_t p = 1;
     while (p * 2 <= b) p *= 2;
-    // states of 16 MiB and more: launches of up to eight families, which the first pass
+    // states of 16 MiB and more: launches of up to sixteen families, which the first pass
     // runs in one tile-sharing group (up to 16 GiB of half spectra)
-    while (p < 8 && first_pass_group(P, dt == PW_C128, 8) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
+    while (p < 16 && first_pass_group(P, dt == PW_C128, 16) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
     return (int)p;
 }
 
@@ -214,6 +215,10 @@ struct pw_ctx_s {
     // schedule asked for by pw_set_schedule (zeros: the tuned or default choice)
     Schedule sched{0, 0, 0};
     int sched_batch = 0;
+    // progress report of long Monte Carlo runs (pw_set_progress)
+    pw_progress_fn progress = nullptr;
+    void* progress_user = nullptr;
+    double progress_every = 0.0;
 };
 
 namespace {
@@ -222,6 +227,17 @@ namespace {
 // it is issued, set by pw_inject_fault for tests of the error paths.
 enum { FAULT_NONE = 0, FAULT_ALLOC = 1, FAULT_LAUNCH = 2, FAULT_COPY = 3 };
 inline bool fault(pw_ctx c, int cls) { return c->fault_class == cls; }
+
+// Progress of a long estimate: the callback set by pw_set_progress, at most once per
+// progress_every seconds of wall time (always when final).
+void report_progress(pw_ctx c, uint64_t families, double M2, double M2_se, bool final) {
+    if (!c->progress) return;
+    static thread_local std::chrono::steady_clock::time_point last{};
+    const auto now = std::chrono::steady_clock::now();
+    if (!final && std::chrono::duration<double>(now - last).count() < c->progress_every) return;
+    last = now;
+    c->progress(c->progress_user, families, M2, M2_se);
+}
 
 // Storage dtype of the data the kernels read for a state of storage dtype dt.
 pw_dtype compute_dtype(pw_ctx c, pw_dtype dt) {
@@ -990,6 +1006,7 @@ pw_status mc_core(pw_ctx c, pw_sampler sampler, double eps, int batch, uint64_t 
         const double S2 = r0.m[0] + run[0].mean;
         const double se2 = sqrt(run[0].var() / run[0].n);
         const double Mse = se2 / (log(2.0) * S2);
+        report_progress(c, drawn + 1, -log2(S2) - n, Mse, false);
         if (batches >= 2 && target_se > 0 && Mse <= target_se) break;
     }
     if (graphs) {
@@ -1983,6 +2000,16 @@ pw_status pw_set_precision(pw_ctx c, pw_prec prec) {
         if (s != PW_OK) return s;
         c->bound = true;
     }
+    return PW_OK;
+}
+
+pw_status pw_set_progress(pw_ctx c, pw_progress_fn fn, void* user, double every_seconds) {
+    pw_status s = check_ctx(c);
+    if (s != PW_OK) return s;
+    if (!(every_seconds >= 0.0)) return fail(PW_ERR_ARG, "every_seconds must be >= 0");
+    c->progress = fn;
+    c->progress_user = user;
+    c->progress_every = every_seconds;
     return PW_OK;
 }
 

@@ -1859,9 +1859,10 @@ int first_pass_group(const Plan& P, bool dbl, int nb) {
     // states of 16 MiB and more (measured: 4-21 % less time per family from 16 MiB to
     // 8 GiB); at least 8 tiles per family, which the grouped numbering needs
     if (P.fused || P.mfma || P.nh - P.k1 < 3 || ((size_t)(dbl ? 16 : 8) << P.n) < ((size_t)16 << 20)) return 1;
-    // groups of eight (measured at n = 28 in launches of 64: 866 -> 807 us per family from
-    // four; n = 30: 4156 -> 4094 us)
-    return nb >= 8 ? 8 : nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
+    // groups of up to sixteen (measured at n = 28 in launches of 64, per family: 870 us in
+    // groups of four, 806 in eights, 780 in sixteens; n = 30: 4156 -> 4094 us from four to
+    // eight)
+    return nb >= 16 ? 16 : nb >= 8 ? 8 : nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
 }
 
 hipError_t sort_by_top_bit(const uint64_t* xs, int n, int nx, uint64_t* xs_sorted, uint32_t* perm, hipStream_t st) {
