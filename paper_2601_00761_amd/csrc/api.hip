@@ -427,7 +427,7 @@ pw_status run_norm(pw_ctx c, double* out) {
 // Evaluate nx families whose x are in device memory (or x0 + i when d_xs is null),
 // results to device array d_out, in launches of the context's launch batch, on st.
 pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, double eps, FamilyRes* d_out,
-                       hipStream_t st) {
+                       hipStream_t st, const uint64_t* d_fpsi = nullptr) {
     const bool dbl = c->cdbl;
     // multi-pass plans: batches leave their partials side by side, one finalize per group
     const bool defer = !c->P.fused;
@@ -442,7 +442,7 @@ pw_status eval_list_on(pw_ctx c, const uint64_t* d_xs, uint64_t x0, int64_t nx, 
         }
         PW_HIP(eval_batch(c->P, dbl, c->max_alpha, c->cpsi, d_xs ? d_xs + i : nullptr, x0 + (uint64_t)i, nb, eps,
                           c->ws + c->L.work, parts + (size_t)pending * c->P.blocks_last, d_out + i, st,
-                          timer_of(c), !defer));
+                          timer_of(c), !defer, d_fpsi ? d_fpsi + i : nullptr));
         pending += nb;
     }
     if (defer && pending > 0) PW_HIP(finalize_families(c->P, c->max_alpha, parts, pending, d_out + g0, st));
@@ -1853,11 +1853,51 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         std::vector<int64_t> fill(start.begin(), start.end() - 1);
         for (int64_t i = 0; i < n_x; ++i) order[(size_t)fill[(size_t)state_idx[i]]++] = i;
     }
+    // classes of states with the same n and dtype, each evaluated as one list whose
+    // launches span its states; inside a class the families go state by state, each
+    // state's in top-bit order (x = 0 first), so that the first pass's tile-sharing groups
+    // meet families of one state and one top bit
+    std::vector<int> cls_of((size_t)nstates, -1);
+    std::vector<std::vector<int>> classes;
+    for (int k = 0; k < nstates; ++k) {
+        if (start[(size_t)k + 1] == start[(size_t)k]) continue;
+        for (size_t q = 0; q < classes.size() && cls_of[(size_t)k] < 0; ++q) {
+            const int r = classes[q][0];
+            if (states[r].n == states[k].n && states[r].dtype == states[k].dtype) {
+                classes[q].push_back(k);
+                cls_of[(size_t)k] = (int)q;
+            }
+        }
+        if (cls_of[(size_t)k] < 0) {
+            cls_of[(size_t)k] = (int)classes.size();
+            classes.push_back({k});
+        }
+    }
+    std::vector<int64_t> seq;   // positions in evaluation order
+    std::vector<int64_t> cstart(classes.size() + 1, 0);
+    seq.reserve((size_t)n_x);
+    for (size_t q = 0; q < classes.size(); ++q) {
+        cstart[q] = (int64_t)seq.size();
+        for (int k : classes[q]) {
+            int64_t cnt[34] = {0};
+            auto key = [&](int64_t pos) { const uint64_t x = xs[pos]; return x ? 64 - __builtin_clzll(x) : 0; };
+            for (int64_t j = start[(size_t)k]; j < start[(size_t)k + 1]; ++j) ++cnt[key(order[(size_t)j]) + 1];
+            for (int b = 0; b < 33; ++b) cnt[b + 1] += cnt[b];
+            const size_t base = seq.size();
+            seq.resize(base + (size_t)(start[(size_t)k + 1] - start[(size_t)k]));
+            for (int64_t j = start[(size_t)k]; j < start[(size_t)k + 1]; ++j) {
+                const int64_t pos = order[(size_t)j];
+                seq[base + (size_t)cnt[key(pos)]++] = pos;
+            }
+        }
+    }
+    cstart[classes.size()] = (int64_t)seq.size();
     // pinned host staging (norms, grouped x, results) and the states' norm slots on the
     // device: the whole call synchronises twice, once for the norm checks of all states
     // and once for all results
     const size_t o_x = align256((size_t)nstates * 2 * sizeof(double));
-    const size_t o_r = o_x + align256((size_t)n_x * sizeof(uint64_t));
+    const size_t o_p = o_x + align256((size_t)n_x * sizeof(uint64_t));
+    const size_t o_r = o_p + align256((size_t)n_x * sizeof(uint64_t));
     const size_t pin_need = o_r + align256((size_t)n_x * sizeof(FamilyRes));
     const size_t nrm_need = (size_t)nstates * 2 * sizeof(double);
     auto allocate = [&]() -> pw_status {
@@ -1905,8 +1945,12 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
     const size_t cap = c->ws_bytes;
     double* hnorm = reinterpret_cast<double*>(c->pin);
     uint64_t* hx = reinterpret_cast<uint64_t*>((char*)c->pin + o_x);
+    uint64_t* hp = reinterpret_cast<uint64_t*>((char*)c->pin + o_p);
     FamilyRes* hres = reinterpret_cast<FamilyRes*>((char*)c->pin + o_r);
-    for (int64_t j = 0; j < n_x; ++j) hx[j] = xs[order[(size_t)j]];
+    for (int64_t j = 0; j < n_x; ++j) {
+        hx[j] = xs[seq[(size_t)j]];
+        hp[j] = (uint64_t)(uintptr_t)states[state_idx[seq[(size_t)j]]].psi;
+    }
     double* dnrm = reinterpret_cast<double*>(c->nrm);
     // bind state k's plan and layout to the context
     auto use_state = [&](int k) -> pw_status {
@@ -1957,23 +2001,33 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
         if (hb) s = fail(PW_ERR_NOT_NORMALIZED, "state %d holds NaN or Inf amplitudes", k);
         else if (!(fabs(nrm - 1.0) <= tol)) s = fail(PW_ERR_NOT_NORMALIZED, "state %d: <psi|psi> = %.17g", k, nrm);
     }
-    // 2. every state's families: x in, results out through the pinned staging, no
-    //    synchronisation until the end (each copy and launch is ordered on the stream)
-    for (int k = 0; k < nstates && s == PW_OK; ++k) {
-        const int64_t j0 = start[(size_t)k], j1 = start[(size_t)k + 1];
-        if (j1 == j0) continue;
-        s = use_state(k);
+    // 2. each class's families as one list (x and state address in, results out through
+    //    the pinned staging), no synchronisation until the end (each copy and launch is
+    //    ordered on the stream); the state addresses take the sorted-list staging, which a
+    //    list in this order does not need
+    for (size_t q = 0; q < classes.size() && s == PW_OK; ++q) {
+        const int64_t j0 = cstart[q], j1 = cstart[q + 1];
+        s = use_state(classes[q][0]);
+        if (s != PW_OK) break;
+        if (fault(c, FAULT_LAUNCH)) {
+            s = fail(PW_ERR_HIP, "kernel launch: injected failure");
+            break;
+        }
+        s = ensure_compute_state(c);
         if (s != PW_OK) break;
         uint64_t* dx = at<uint64_t>(c, c->L.xs);
+        uint64_t* dp = at<uint64_t>(c, c->L.xsort);
         FamilyRes* dr = at<FamilyRes>(c, c->L.xres);
         for (int64_t j = j0; j < j1 && s == PW_OK; j += c->L.xcap) {
             const int64_t nb = (j1 - j) < c->L.xcap ? (j1 - j) : c->L.xcap;
             if (hipMemcpyAsync(dx, hx + j, (size_t)nb * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream) !=
-                hipSuccess) {
+                    hipSuccess ||
+                hipMemcpyAsync(dp, hp + j, (size_t)nb * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream) !=
+                    hipSuccess) {
                 s = fail(PW_ERR_HIP, "x list copy failed");
                 break;
             }
-            s = eval_device(c, dx, 0, nb, eps, dr);
+            s = eval_list_on(c, dx, 0, nb, eps, dr, c->stream, dp);
             if (s != PW_OK) break;
             if (hipMemcpyAsync(hres + j, dr, (size_t)nb * sizeof(FamilyRes), hipMemcpyDeviceToHost, c->stream) !=
                 hipSuccess)
@@ -1983,7 +2037,7 @@ pw_status pw_eval_states(pw_ctx c, int nstates, const pw_state_ref* states, cons
     if (s == PW_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = fail(PW_ERR_HIP, "synchronisation failed");
     s = restore(s);
     if (s != PW_OK) return s;
-    for (int64_t j = 0; j < n_x; ++j) memcpy(out + order[(size_t)j], hres + j, sizeof(FamilyRes));
+    for (int64_t j = 0; j < n_x; ++j) memcpy(out + seq[(size_t)j], hres + j, sizeof(FamilyRes));
     return PW_OK;
 }
 

@@ -114,9 +114,11 @@ struct LaunchTimer {
 // With finalize == false a multi-pass plan stops at the partials (family i at
 // parts + i * blocks_last) and out is not written: several batches can then be
 // finalized by one finalize_families call.  Single-workgroup plans always write out.
+// fpsi (with xs only): device array of nb state addresses, family i reads the state at
+// fpsi[i] instead of psi (several states of the same n and dtype in one launch).
 hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, const uint64_t* xs, uint64_t x0,
                       int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
-                      const LaunchTimer* tm = nullptr, bool finalize = true);
+                      const LaunchTimer* tm = nullptr, bool finalize = true, const uint64_t* fpsi = nullptr);
 // Per-family results of nfam families whose partials are contiguous in parts.
 hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* parts, int64_t nfam, FamilyRes* out,
                              hipStream_t st);

@@ -357,6 +357,13 @@ struct AccD {
     unsigned cnt;
 };
 
+// The state a family reads: one state for the launch, or (lists over several states of
+// one size) fpsi[slot], the device address of that family's state.
+template <typename T>
+__device__ __forceinline__ const T* state_of(const T* psi, const uint64_t* __restrict__ fpsi, uint32_t slot) {
+    return fpsi ? reinterpret_cast<const T*>(fpsi[slot]) : psi;
+}
+
 // Reductions over the thread's points.  Each point carries two magnitudes:
 // x = 0: |Re G + Im G|, |Re G - Im G|;  x != 0: 2|Re G|, 2|Im G|.  For x != 0 the
 // squares are accumulated as t = (Re G)^2 and scaled by the exact factor 4 at the
@@ -552,8 +559,8 @@ __device__ __forceinline__ FamilyRes finish(const AccD& a, uint64_t x, int n) {
 // Whole family in one workgroup (n - 1 = K).  Grid: one block per family.
 template <typename R, int TL, int RL, int MOM>
 __global__ void __launch_bounds__(1 << TL)
-k_fused(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
-        FamilyRes* __restrict__ out) {
+k_fused(const cx<R>* __restrict__ psi, const uint64_t* __restrict__ fpsi, int n, const uint64_t* __restrict__ xs,
+        uint64_t x0, R eps, FamilyRes* __restrict__ out) {
     constexpr int K = TL + RL;
     constexpr int NT = 1 << TL;
     __shared__ cx<R> lds[Lds<K>::elems];
@@ -562,7 +569,7 @@ k_fused(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     const uint32_t slot = blockIdx.x;
     const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);  // device lists: x mod 2^n
     R re[1 << RL], im[1 << RL];
-    load_products<R, TL, RL>(psi, n - 1, (uint32_t)x, 0u, re, im);
+    load_products<R, TL, RL>(state_of(psi, fpsi, slot), n - 1, (uint32_t)x, 0u, re, im);
     if constexpr (sizeof(R) == 8) lg2_table_init(lg2t);
     tile_fwht<R, TL, RL, 0>(re, im, lds);
     const AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, lg2t), shw);
@@ -830,8 +837,8 @@ k_fused_store(const cx<R>* __restrict__ psi, int n, uint64_t x, cx<R>* __restric
 // Requires tiles % 8 == 0; workgroups of the padding slots (>= nb) return at once.
 template <typename R, int TL, int RL, bool SPLIT = false, bool HSRC = false, int GRP = 1>
 __global__ void __launch_bounds__(1 << TL)
-k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0,
-        cx<R>* __restrict__ work, int nb) {
+k_first(const cx<R>* __restrict__ psi, const uint64_t* __restrict__ fpsi, int n, const uint64_t* __restrict__ xs,
+        uint64_t x0, cx<R>* __restrict__ work, int nb) {
     constexpr int K = TL + RL;
     __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT, RL>::v];
     const int nh = n - 1;
@@ -848,9 +855,10 @@ k_first(const cx<R>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, u
     }
     const uint32_t x = (uint32_t)((xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull));
     R re[1 << RL], im[1 << RL];
-    if constexpr (HSRC) load_reduced<R, TL, RL>(psi, n, x, tile, re, im);
-    else if (x >= (1u << K)) load_products_hi<R, TL, RL>(psi, x, tile, re, im);
-    else load_products<R, TL, RL>(psi, nh, x, tile, re, im);
+    const cx<R>* ps = state_of(psi, fpsi, slot);
+    if constexpr (HSRC) load_reduced<R, TL, RL>(ps, n, x, tile, re, im);
+    else if (x >= (1u << K)) load_products_hi<R, TL, RL>(ps, x, tile, re, im);
+    else load_products<R, TL, RL>(ps, nh, x, tile, re, im);
     tile_fwht<R, TL, RL, 0, SPLIT>(re, im, lds);
     store_tile<R, TL, RL, SPLIT>(work + ((size_t)slot << nh) + ((size_t)tile << K), re, im);
 }
@@ -1120,8 +1128,8 @@ __device__ __forceinline__ void load_products_mfma(const cx<float>* __restrict__
 // Whole family in one workgroup on the matrix cores (n - 1 = K = 8 + LB + LW).
 template <int LB, int LW, int MOM>
 __global__ void __launch_bounds__(64 << LW)
-k_fused_mfma(const cx<float>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0, float eps,
-             FamilyRes* __restrict__ out) {
+k_fused_mfma(const cx<float>* __restrict__ psi, const uint64_t* __restrict__ fpsi, int n,
+             const uint64_t* __restrict__ xs, uint64_t x0, float eps, FamilyRes* __restrict__ out) {
     using T = MfmaTile<LB, LW>;
     constexpr int NT = 64 << LW;
     __shared__ cx<float> lds[LW > 0 ? T::lds_elems : 1];
@@ -1129,7 +1137,7 @@ k_fused_mfma(const cx<float>* __restrict__ psi, int n, const uint64_t* __restric
     const uint32_t slot = blockIdx.x;
     const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);
     float re[T::N], im[T::N];
-    load_products_mfma<T>(psi, n - 1, (uint32_t)x, 0u, re, im);
+    load_products_mfma<T>(state_of(psi, fpsi, slot), n - 1, (uint32_t)x, 0u, re, im);
     T::run(re, im, lds);
     constexpr int RL = LB + 2;
     const AccD tot = block_reduce<NT, MOM>(reduce_points<float, RL, MOM>(re, im, x == 0, eps, nullptr), shw);
@@ -1139,15 +1147,15 @@ k_fused_mfma(const cx<float>* __restrict__ psi, int n, const uint64_t* __restric
 // First pass of a multi-pass transform on the matrix cores: products + the low 12 index
 // bits of one tile (4 waves x 4 blocks); the tile is written back in index order.
 __global__ void __launch_bounds__(256)
-k_first_mfma(const cx<float>* __restrict__ psi, int n, const uint64_t* __restrict__ xs, uint64_t x0,
-             cx<float>* __restrict__ work) {
+k_first_mfma(const cx<float>* __restrict__ psi, const uint64_t* __restrict__ fpsi, int n,
+             const uint64_t* __restrict__ xs, uint64_t x0, cx<float>* __restrict__ work) {
     using T = MfmaTile<2, 2>;
     __shared__ cx<float> lds[T::lds_elems];
     const int nh = n - 1;
     const uint32_t tile = blockIdx.x, slot = blockIdx.y;
     const uint32_t x = (uint32_t)((xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull));
     float re[T::N], im[T::N];
-    load_products_mfma<T>(psi, nh, x, tile, re, im);
+    load_products_mfma<T>(state_of(psi, fpsi, slot), nh, x, tile, re, im);
     T::run(re, im, lds);
     const uint32_t l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4, c = l & 15;
     cx<float>* dst = work + ((size_t)slot << nh) + ((size_t)tile << T::K);
@@ -1400,27 +1408,27 @@ constexpr int COL_RL = 4;
 #endif
 
 template <typename R, int K, int MOM>
-hipError_t launch_fused_k(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
-                          hipStream_t st, const LaunchTimer* tm) {
+hipError_t launch_fused_k(const void* psi, const uint64_t* fpsi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps,
+                          FamilyRes* out, hipStream_t st, const LaunchTimer* tm) {
     constexpr int RL0 = K < 4 ? K : 4;
     constexpr int TL = K == 13 ? 9 : K - RL0;
     constexpr int RL = K - TL;
-    PW_LAUNCH(tm, 0, nb, (k_fused<R, TL, RL, MOM>), dim3(nb), dim3(1 << TL), st, (const cx<R>*)psi, n, xs, x0, eps,
-              out);
+    PW_LAUNCH(tm, 0, nb, (k_fused<R, TL, RL, MOM>), dim3(nb), dim3(1 << TL), st, (const cx<R>*)psi, fpsi, n, xs, x0,
+              eps, out);
     return hipGetLastError();
 }
 
 template <typename R, int MOM>
-hipError_t launch_fused(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps, FamilyRes* out,
-                        hipStream_t st, const LaunchTimer* tm) {
+hipError_t launch_fused(const void* psi, const uint64_t* fpsi, int n, const uint64_t* xs, uint64_t x0, int nb, R eps,
+                        FamilyRes* out, hipStream_t st, const LaunchTimer* tm) {
     switch (n - 1) {
 #define PW_CASE(K) \
-    case K: return launch_fused_k<R, K, MOM>(psi, n, xs, x0, nb, eps, out, st, tm);
+    case K: return launch_fused_k<R, K, MOM>(psi, fpsi, n, xs, x0, nb, eps, out, st, tm);
         PW_CASE(0) PW_CASE(1) PW_CASE(2) PW_CASE(3) PW_CASE(4) PW_CASE(5) PW_CASE(6)
         PW_CASE(7) PW_CASE(8) PW_CASE(9) PW_CASE(10) PW_CASE(11) PW_CASE(12)
 #undef PW_CASE
         case 13:
-            if constexpr (sizeof(R) == 4) return launch_fused_k<R, 13, MOM>(psi, n, xs, x0, nb, eps, out, st, tm);
+            if constexpr (sizeof(R) == 4) return launch_fused_k<R, 13, MOM>(psi, fpsi, n, xs, x0, nb, eps, out, st, tm);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
@@ -1506,13 +1514,13 @@ hipError_t launch_column(int ktile, int s, int nh, int nb, cx<R>* work, int n, i
 }
 
 template <int MOM>
-hipError_t launch_fused_mfma(const void* psi, int n, const uint64_t* xs, uint64_t x0, int nb, float eps, FamilyRes* out,
-                             hipStream_t st, const LaunchTimer* tm) {
+hipError_t launch_fused_mfma(const void* psi, const uint64_t* fpsi, int n, const uint64_t* xs, uint64_t x0, int nb,
+                             float eps, FamilyRes* out, hipStream_t st, const LaunchTimer* tm) {
     switch (n - 1) {
 #define PW_MF(K, LB, LW)                                                                                           \
     case K:                                                                                                        \
-        PW_LAUNCH(tm, 0, nb, (k_fused_mfma<LB, LW, MOM>), dim3(nb), dim3(64 << LW), st, (const cx<float>*)psi, n, xs, \
-                  x0, eps, out);                                                                                   \
+        PW_LAUNCH(tm, 0, nb, (k_fused_mfma<LB, LW, MOM>), dim3(nb), dim3(64 << LW), st, (const cx<float>*)psi, fpsi, \
+                  n, xs, x0, eps, out);                                                                            \
         return hipGetLastError();
         PW_MF(8, 0, 0) PW_MF(9, 1, 0) PW_MF(10, 2, 0) PW_MF(11, 2, 1) PW_MF(12, 2, 2) PW_MF(13, 3, 2)
 #undef PW_MF
@@ -1523,48 +1531,49 @@ hipError_t launch_fused_mfma(const void* psi, int n, const uint64_t* xs, uint64_
 // First pass over nb families, with the tile-sharing groups where first_pass_group
 // asks for them.
 template <typename R, int TL, int RL, bool SPLIT>
-void launch_first(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, void* work,
-                  hipStream_t st, const LaunchTimer* tm) {
+void launch_first(const Plan& P, const void* psi, const uint64_t* fpsi, const uint64_t* xs, uint64_t x0, int nb,
+                  void* work, hipStream_t st, const LaunchTimer* tm) {
     const uint32_t tiles = 1u << (P.nh - TL - RL);
     const int grp = first_pass_group(P, sizeof(R) == 8, nb);
     const uint32_t blocks = tiles * (uint32_t)((nb + grp - 1) / grp * grp);
     if (grp == 16)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 16>), dim3(blocks), dim3(1 << TL), st,
-                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+                  (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
     else if (grp == 8)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 8>), dim3(blocks), dim3(1 << TL), st,
-                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+                  (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
     else if (grp == 4)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 4>), dim3(blocks), dim3(1 << TL), st,
-                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+                  (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
     else if (grp == 2)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 2>), dim3(blocks), dim3(1 << TL), st,
-                  (const cx<R>*)psi, P.n, xs, x0, (cx<R>*)work, nb);
+                  (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
     else
-        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT>), dim3(tiles, nb), dim3(1 << TL), st, (const cx<R>*)psi, P.n,
-                  xs, x0, (cx<R>*)work, nb);
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT>), dim3(tiles, nb), dim3(1 << TL), st, (const cx<R>*)psi, fpsi,
+                  P.n, xs, x0, (cx<R>*)work, nb);
 }
 
 template <typename R, int MOM>
-hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint64_t x0, int nb, double eps,
-                        void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st, const LaunchTimer* tm,
-                        bool finalize) {
+hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* fpsi, const uint64_t* xs, uint64_t x0, int nb,
+                        double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
+                        const LaunchTimer* tm, bool finalize) {
     if (nb <= 0) return hipSuccess;
+    if (fpsi && !xs) return hipErrorInvalidValue;   // per-family states come with a list
     const R e = (R)eps;
     if constexpr (sizeof(R) == 4) {
-        if (P.fused && P.mfma && P.nh >= 8) return launch_fused_mfma<MOM>(psi, P.n, xs, x0, nb, e, out, st, tm);
+        if (P.fused && P.mfma && P.nh >= 8) return launch_fused_mfma<MOM>(psi, fpsi, P.n, xs, x0, nb, e, out, st, tm);
     }
-    if (P.fused) return launch_fused<R, MOM>(psi, P.n, xs, x0, nb, e, out, st, tm);
+    if (P.fused) return launch_fused<R, MOM>(psi, fpsi, P.n, xs, x0, nb, e, out, st, tm);
     const uint32_t tiles = 1u << (P.nh - P.k1);
     if constexpr (sizeof(R) == 4) {
         if (P.mfma) {
             if (P.k1 != K_FIRST) return hipErrorInvalidValue;
-            PW_LAUNCH(tm, 1, nb, k_first_mfma, dim3(tiles, nb), dim3(256), st, (const cx<float>*)psi, P.n, xs, x0,
-                      (cx<float>*)work);
+            PW_LAUNCH(tm, 1, nb, k_first_mfma, dim3(tiles, nb), dim3(256), st, (const cx<float>*)psi, fpsi, P.n, xs,
+                      x0, (cx<float>*)work);
             goto first_done;
         }
         if (P.k1 == 15) {
-            launch_first<float, 10, 5, true>(P, psi, xs, x0, nb, work, st, tm);
+            launch_first<float, 10, 5, true>(P, psi, fpsi, xs, x0, nb, work, st, tm);
             goto first_done;
         }
     }
@@ -1577,7 +1586,7 @@ hipError_t eval_batch_t(const Plan& P, const void* psi, const uint64_t* xs, uint
         PW_LAUNCH(tm, 1, nb, (k_first_shared<R, 8, 4>), dim3(tiles, nb / fam), dim3(256), st, (const cx<R>*)psi, P.n,
                   x0, fam, (cx<R>*)work);
     } else {
-        launch_first<R, 8, 4, false>(P, psi, xs, x0, nb, work, st, tm);
+        launch_first<R, 8, 4, false>(P, psi, fpsi, xs, x0, nb, work, st, tm);
     }
 first_done:
     hipError_t err = hipGetLastError();
@@ -1627,13 +1636,14 @@ hipError_t transform_one_t(const Plan& P, const void* psi, uint64_t x, void* wor
     if constexpr (sizeof(R) == 4) {
         if (P.k1 == 15) {
             hipLaunchKernelGGL((k_first<float, 10, 5, true>), dim3(1u << (nh - 15), 1), dim3(1024), 0, st,
-                               (const cx<float>*)psi, P.n, (const uint64_t*)nullptr, x, (cx<float>*)work, 1);
+                               (const cx<float>*)psi, (const uint64_t*)nullptr, P.n, (const uint64_t*)nullptr, x,
+                               (cx<float>*)work, 1);
             done = true;
         }
     }
     if (!done)
         hipLaunchKernelGGL((k_first<R, 8, 4>), dim3(1u << (nh - K_FIRST), 1), dim3(256), 0, st, (const cx<R>*)psi,
-                           P.n, (const uint64_t*)nullptr, x, (cx<R>*)work, 1);
+                           (const uint64_t*)nullptr, P.n, (const uint64_t*)nullptr, x, (cx<R>*)work, 1);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
@@ -1775,12 +1785,13 @@ Plan make_plan_impl(int n, bool dbl, bool allow15) {
 
 hipError_t eval_batch(const Plan& P, bool dbl, int max_alpha, const void* psi, const uint64_t* xs, uint64_t x0,
                       int nb, double eps, void* work, FamilyRes* parts, FamilyRes* out, hipStream_t st,
-                      const LaunchTimer* tm, bool finalize) {
+                      const LaunchTimer* tm, bool finalize, const uint64_t* fpsi) {
     if (dbl)
-        return max_alpha >= 4 ? eval_batch_t<double, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize)
-                              : eval_batch_t<double, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize);
-    return max_alpha >= 4 ? eval_batch_t<float, 4>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize)
-                          : eval_batch_t<float, 2>(P, psi, xs, x0, nb, eps, work, parts, out, st, tm, finalize);
+        return max_alpha >= 4
+                   ? eval_batch_t<double, 4>(P, psi, fpsi, xs, x0, nb, eps, work, parts, out, st, tm, finalize)
+                   : eval_batch_t<double, 2>(P, psi, fpsi, xs, x0, nb, eps, work, parts, out, st, tm, finalize);
+    return max_alpha >= 4 ? eval_batch_t<float, 4>(P, psi, fpsi, xs, x0, nb, eps, work, parts, out, st, tm, finalize)
+                          : eval_batch_t<float, 2>(P, psi, fpsi, xs, x0, nb, eps, work, parts, out, st, tm, finalize);
 }
 
 hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* parts, int64_t nfam, FamilyRes* out,
@@ -1814,8 +1825,8 @@ hipError_t eval_reduced_mp_t(const Plan& P, const void* D, uint64_t x0, int nb, 
     if (P.fused || P.k1 != K_FIRST) return hipErrorInvalidValue;
     const R e = (R)eps;
     const uint32_t tiles = 1u << (P.nh - P.k1);
-    hipLaunchKernelGGL((k_first<R, 8, 4, false, true>), dim3(tiles, nb), dim3(256), 0, st, (const cx<R>*)D, P.n,
-                       nullptr, x0, (cx<R>*)work, nb);
+    hipLaunchKernelGGL((k_first<R, 8, 4, false, true>), dim3(tiles, nb), dim3(256), 0, st, (const cx<R>*)D,
+                       (const uint64_t*)nullptr, P.n, (const uint64_t*)nullptr, x0, (cx<R>*)work, nb);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i = 0; i < P.npass; ++i) {
