@@ -7,7 +7,7 @@ Headline workload: an N = 28 T-doped random Clifford state in complex64 (2 GiB;
 random qubit after every eta = 16 of them, N_T = 2N = 56), Clifford-preconditioned by the
 library (2N = 56 random brick-wall Clifford layers, timed), then Monte Carlo over
 X-bitstrings: x = 0 plus x drawn from the exact x-marginal on the device, evaluated in
-launches of 64 families (product, transform over all 2^28 z, moments, Shannon term,
+launches of 128 families (product, transform over all 2^28 z, moments, Shannon term,
 nullity count), and the estimate of S_2, M_2, M_1 with its standard error.  One step is
 one Monte Carlo estimate over 2048 drawn families (plus x = 0); value = Pauli strings
 evaluated per second (families x 2^28) over the timed steps, the state resident in HBM.
@@ -452,7 +452,7 @@ def note(msg):
 
 
 HEAD_N = 28
-HEAD_BATCH = 64           # families per launch (a lent workspace of 64 families)
+HEAD_BATCH = 128          # families per launch (a lent workspace of 128 families)
 HEAD_FAMILIES = 2048      # drawn families per step
 
 
@@ -496,7 +496,7 @@ def headline_state(pw, torch, stream, eta):
 
 def headline_steps(pw, torch, ctx, seed, steps, warmup):
     """Monte Carlo steps on the headline state: each step draws HEAD_FAMILIES x from the exact
-    marginal (device sampler) and evaluates them with x = 0, in launches of 64 families,
+    marginal (device sampler) and evaluates them with x = 0, in launches of HEAD_BATCH families,
     eagerly, with HIP events attached to every launch of the timed steps (the kernels'
     own dispatch intervals on the context stream)."""
     pw.pw_set_graphs(ctx.h, 0)

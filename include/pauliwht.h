@@ -327,7 +327,7 @@ PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out)
  * variant that applies -- first pass over the low 12 index bits, or (single precision,
  * n - 1 = 16..27) over 15 bits; column tiles of 12 or 13 bits (single precision), or of
  * 15 bits after a 15-bit first pass -- crossed with first-pass tile-sharing groups of 1, 2,
- * 4, 8 and 16 families.  Stage 2, for the fastest: up to 6 launch sizes (the workspace batch
+ * 4, ..., 128 families (up to the launch size).  Stage 2, for the fastest: up to 6 launch sizes (the workspace batch
  * and its halvings, none below the group).  The result is recorded per (device, n,
  * arithmetic) for every context of the process (pw_autotune_save / pw_autotune_load keep
  * it across processes) and takes effect on this context unless pw_set_schedule fixed one.
@@ -337,7 +337,7 @@ PW_API pw_status pw_mixed(pw_ctx ctx, int n_a, double eps, pw_mixed_result* out)
 PW_API pw_status pw_autotune(pw_ctx ctx, int* best_batch, int* candidates, double* us_per_family, int* n_candidates);
 
 /* Fix the schedule of this context (0 = the tuned or default choice for that part):
- * first_bits 12 or 15, column_tile_bits 12, 13 or 15, group 1, 2, 4, 8 or 16 families per
+ * first_bits 12 or 15, column_tile_bits 12, 13 or 15, group 1, 2, 4, ..., 128 families per
  * first-pass tile-sharing group, batch families per launch (at most the workspace's).
  * PW_ERR_UNSUPPORTED when the schedule does not apply to the bound state; a later bind of a
  * state it does not apply to takes the default plan. */

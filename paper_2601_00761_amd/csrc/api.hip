@@ -1606,7 +1606,7 @@ std::vector<Schedule> schedule_candidates(pw_ctx c) {
         const Plan P = make_plan_sched(c->n, c->cdbl, Schedule{pk.first, pk.second, 1}, &ok);
         if (!ok) continue;
         const bool can_group = P.nh - P.k1 >= 3;
-        for (int g : {1, 2, 4, 8, 16}) {
+        for (int g = 1; g <= GROUP_MAX; g *= 2) {
             if (g > 1 && (!can_group || g > c->batch)) continue;
             out.push_back(Schedule{pk.first, pk.second, g});
         }
@@ -1719,7 +1719,7 @@ pw_status pw_set_schedule(pw_ctx c, int first_bits, int column_tile_bits, int gr
     if (s != PW_OK) return s;
     if ((first_bits != 0 && first_bits != 12 && first_bits != 15) ||
         (column_tile_bits != 0 && column_tile_bits != 12 && column_tile_bits != 13 && column_tile_bits != 15) ||
-        (group != 0 && group != 1 && group != 2 && group != 4 && group != 8 && group != 16) || batch < 0 ||
+        group < 0 || group > GROUP_MAX || (group & (group - 1)) != 0 || batch < 0 ||
         batch > MAX_BATCH)
         return fail(PW_ERR_ARG, "schedule (%d, %d, %d, %d) outside the supported values", first_bits,
                     column_tile_bits, group, batch);

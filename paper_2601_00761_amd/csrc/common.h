@@ -63,9 +63,13 @@ struct Plan {
     int grp_req;
 };
 
+// Largest first-pass tile-sharing group (families that read one state tile once).
+constexpr int GROUP_MAX = 128;
+
 // A transform schedule: first-pass bits (12, or 15 for single precision n - 1 = 16..27),
 // column-tile bits (12; 13 single precision; 15 single precision after a 15-bit first pass
-// with 9..12 bits left), first-pass group (1, 2, 4, 8, 16); 0 = the default choice.
+// with 9..12 bits left), first-pass group (a power of two up to GROUP_MAX); 0 = the default
+// choice.
 struct Schedule {
     int first_bits, column_tile_bits, group;
 };

@@ -1536,7 +1536,16 @@ void launch_first(const Plan& P, const void* psi, const uint64_t* fpsi, const ui
     const uint32_t tiles = 1u << (P.nh - TL - RL);
     const int grp = first_pass_group(P, sizeof(R) == 8, nb);
     const uint32_t blocks = tiles * (uint32_t)((nb + grp - 1) / grp * grp);
-    if (grp == 16)
+    if (grp == 128)
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 128>), dim3(blocks), dim3(1 << TL), st,
+                  (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
+    else if (grp == 64)
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 64>), dim3(blocks), dim3(1 << TL), st,
+                  (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
+    else if (grp == 32)
+        PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 32>), dim3(blocks), dim3(1 << TL), st,
+                  (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
+    else if (grp == 16)
         PW_LAUNCH(tm, 1, nb, (k_first<R, TL, RL, SPLIT, false, 16>), dim3(blocks), dim3(1 << TL), st,
                   (const cx<R>*)psi, fpsi, P.n, xs, x0, (cx<R>*)work, nb);
     else if (grp == 8)
@@ -1665,8 +1674,7 @@ Plan make_plan(int n, bool dbl) { return make_plan_impl(n, dbl, true); }
 Plan make_plan_sched(int n, bool dbl, const Schedule& sc, bool* honoured) {
     Plan P = make_plan_impl(n, dbl, true);
     bool ok = true;
-    if (sc.group != 0 && sc.group != 1 && sc.group != 2 && sc.group != 4 && sc.group != 8 && sc.group != 16)
-        ok = false;
+    if (sc.group < 0 || sc.group > GROUP_MAX || (sc.group & (sc.group - 1)) != 0) ok = false;
     if (!P.fused && ok && (sc.first_bits != 0 || sc.column_tile_bits != 0)) {
         const int nh = n - 1;
         int k1 = sc.first_bits ? sc.first_bits : P.k1;
@@ -1870,10 +1878,13 @@ int first_pass_group(const Plan& P, bool dbl, int nb) {
     // states of 16 MiB and more (measured: 4-21 % less time per family from 16 MiB to
     // 8 GiB); at least 8 tiles per family, which the grouped numbering needs
     if (P.fused || P.mfma || P.nh - P.k1 < 3 || ((size_t)(dbl ? 16 : 8) << P.n) < ((size_t)16 << 20)) return 1;
-    // groups of up to sixteen (measured at n = 28 in launches of 64, per family: 870 us in
-    // groups of four, 806 in eights, 780 in sixteens; n = 30: 4156 -> 4094 us from four to
-    // eight)
-    return nb >= 16 ? 16 : nb >= 8 ? 8 : nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
+    // the whole launch as one group, up to 128 families (measured at n = 28, per family of the
+    // first pass: launches of 64 in groups of 4: 870 us, 8: 806, 16: 780 (whole path), 32: 436,
+    // 64: 416; launches of 128 in groups of 64: 428, of 128: 404; n = 30: 4156 -> 4094 us from
+    // groups of four to eight)
+    int g = 1;
+    while (g * 2 <= nb && g * 2 <= GROUP_MAX) g *= 2;
+    return g;
 }
 
 hipError_t sort_by_top_bit(const uint64_t* xs, int n, int nx, uint64_t* xs_sorted, uint32_t* perm, hipStream_t st) {

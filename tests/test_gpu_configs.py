@@ -6,8 +6,8 @@
   only the oracle): complex128 at 1e-10 relative with the nullity count exact, complex64
   within the first-order single-precision bound summed over every family.
 - N = 28 T-doped Clifford state (eta = 4, N_T = 56), preconditioned by the library with
-  56 brick-wall layers, in the benchmark's launch configuration (a lent workspace of 64
-  families): x = 0 and the first 15 draws of the library's exact-marginal sampler,
+  56 brick-wall layers, in the benchmark's launch configuration (a lent workspace of 128
+  families, one first-pass group per launch): x = 0 and the first 15 draws of the library's exact-marginal sampler,
   evaluated by the library and by the oracle on the same state bytes (copied back).
 - N = 30 T-doped Clifford state (eta = 8, N_T = 60): the same for x = 0 and 3 draws.
 
@@ -70,8 +70,8 @@ def config3():
     import torch
     n, eta = 28, 4
     seed = synth.SEED_BASE + 3 + 100 * eta
-    log("config3: T-doped n=%d eta=%d on the device, 64-family workspace" % (n, eta))
-    ctx = _tdoped_on_device(n, eta, 2 * n, seed, 64)
+    log("config3: T-doped n=%d eta=%d on the device, 128-family workspace" % (n, eta))
+    ctx = _tdoped_on_device(n, eta, 2 * n, seed, 128)
     ctx.precondition(2 * n, seed + 1)
     draws = ctx.sample_x(pw.PW_SAMPLER_MARGINAL_NZ, seed + 2, 0, 15)
     xs = np.concatenate([[0], draws]).astype(np.uint64)

@@ -94,18 +94,19 @@ def test_psi_m_closed_forms_largest_sizes(n):
 def test_scrambled_psi_m_monte_carlo_n28():
     # M_2(C psi_m) = M_2(psi_m) = (N/2) log2(4/3): preconditioning, marginal sampling and the
     # estimator at full size, with the library's default launches and with the benchmark's
-    # lent workspace of 64 families (one launch per 64-draw step): the same numbers
+    # lent workspace of 128 families (one launch, one first-pass group, per 128-draw step):
+    # the same numbers
     n = 28
     psi = psi_m_sparse(n)
     k, q, m = synth.gates_to_arrays(synth.random_brickwall_clifford(n, 2 * n, synth.SEED_BASE + 28))
     out = []
-    for x_batch in (None, 64):
+    for x_batch in (None, 128):
         log("scrambled psi_m MC n=%d gates=%d x_batch=%s" % (n, len(k), x_batch))
         ctx = pw.Context(0)
         ctx.upload(psi, pw.PW_C64, x_batch=x_batch)
         ctx.apply_gates(k, q, m)
         pw.pw_set_graphs(ctx.h, 1)
-        out.append(ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 64, 4097, 2e-3, 7))
+        out.append(ctx.mc(pw.PW_SAMPLER_MARGINAL_NZ, 1e-4, 128, 4097, 2e-3, 7))
         ctx.close()
         del ctx
     for key in ("M", "M_se", "S", "n_samples", "M1"):
@@ -246,19 +247,20 @@ def test_tile_sharing_groups_keep_list_order_and_values(n, dtype):
         assert int(g["nu"][i]) == int(r["nu"][j])
 
 
-@pytest.mark.parametrize("n,dtype,xb", [(21, 1, 2), (21, 1, 8), (20, 0, 8)])
+@pytest.mark.parametrize("n,dtype,xb", [(21, 1, 2), (21, 1, 8), (20, 0, 8), (21, 1, 128)])
 def test_tile_sharing_group_sizes_and_padding(n, dtype, xb):
-    # a lent workspace fixes the launch: two families (groups of two; an odd list ends
-    # with a single family), or eight (two groups of four; a 29-family list ends with a
-    # launch of five, padded to two groups whose unused workgroups return at once).  A
-    # device list of 4099 families crosses the 4096-family staging of the sort.  All
-    # bitwise equal to one family per launch.
+    # a lent workspace fixes the launch, and a launch is one group of up to 128 families:
+    # two families (an odd list ends with a single family), eight (a 29-family list ends
+    # with a launch of five, one group of four padded to two whose unused workgroups return
+    # at once), or 128 (a 300-family list: groups of 128, 128, then 44 families in two
+    # groups of 32, the second padded).  A device list of 4099 families crosses the
+    # 4096-family staging of the sort.  All bitwise equal to one family per launch.
     import torch
     from gpu_util import as_input, make_ctx
     eps = 1e-7 if dtype == 0 else 1e-4
     psi = as_input(synth.haar_state(n, 2700 + n), dtype)
     rng = np.random.default_rng(2700 + n + xb)
-    xs = rng.integers(0, 1 << n, size=29, dtype=np.uint64)
+    xs = rng.integers(0, 1 << n, size=300 if xb == 128 else 29, dtype=np.uint64)
     log("group sizes n=%d dtype=%d x_batch=%d" % (n, dtype, xb))
     ctx1 = make_ctx(psi, dtype, x_batch=1)
     ctx = make_ctx(psi, dtype, x_batch=xb)
