@@ -370,6 +370,7 @@ def multistate_leg(pw, torch, stream):
 
 
 LEARNED_N = 30
+LEARNED_BATCH = 16
 
 
 def learned_leg(pw, torch, stream, kind, draws, pilot):
@@ -399,6 +400,9 @@ def learned_leg(pw, torch, stream, kind, draws, pilot):
     else:
         psi[0] = 1.0
     ctx = pw.Context(0, stream)
+    # a lent workspace of 16 families (64 GiB of half spectra; the library's default takes
+    # four at this size): launches of 16 with one first-pass group each
+    ctx.reserve(n, pw.PW_C64, LEARNED_BATCH)
     ctx.bind(psi, pw.PW_C64)
     pw.pw_set_moments(ctx.h, 2)
     if kind != "psi_m":
