@@ -1271,7 +1271,16 @@ k_scatter_res(const FamilyRes* __restrict__ in, const uint32_t* __restrict__ per
     if (j < nx) out[perm[j]] = in[j];
 }
 
+// Neumaier's compensated sum: s holds the running total, c the low-order parts that the
+// additions lost; the sum is s + c.
+__device__ __forceinline__ void comp_add(double& s, double& c, double v) {
+    const double t = s + v;
+    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+}
+
 // Per-family fixed-order sum of the final pass's partials.  Grid: one wave per family.
+// Each lane's run over the partials is compensated; the wave tree (6 levels) is not.
 template <int MOM>
 __global__ void __launch_bounds__(64)
 k_finalize(const FamilyRes* __restrict__ parts, int nblk, int n, FamilyRes* __restrict__ out) {
@@ -1280,7 +1289,22 @@ k_finalize(const FamilyRes* __restrict__ parts, int nblk, int n, FamilyRes* __re
     a.s1 = a.ent = a.s2 = a.s3 = a.s4 = 0.0;
     a.gap = -1.0;
     a.cnt = 0u;
-    for (int i = threadIdx.x; i < nblk; i += 64) add_to(a, acc_of(p[i]));
+    double c1 = 0.0, ce = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 64) {
+        const AccD b = acc_of(p[i]);
+        comp_add(a.s1, c1, b.s1);
+        comp_add(a.ent, ce, b.ent);
+        comp_add(a.s2, c2, b.s2);
+        comp_add(a.s3, c3, b.s3);
+        comp_add(a.s4, c4, b.s4);
+        a.gap = fmax(a.gap, b.gap);
+        a.cnt += b.cnt;
+    }
+    a.s1 += c1;
+    a.ent += ce;
+    a.s2 += c2;
+    a.s3 += c3;
+    a.s4 += c4;
     a = wave_reduce<64>(a);
     if (threadIdx.x == 0) out[blockIdx.x] = finish<MOM>(a, p[0].x, n);
 }
@@ -1309,33 +1333,55 @@ __device__ __forceinline__ void add_sums(SweepSums& a, const SweepSums& b) {
     }
 }
 
+// Compensated run of one thread over SweepSums values (the sums of each field).
+struct SweepComp {
+    double S[3], L, P, Snz[3], Q[3];
+};
+
+__device__ __forceinline__ void zero_comp(SweepComp& c) {
+    for (int a = 0; a < 3; ++a) c.S[a] = c.Snz[a] = c.Q[a] = 0.0;
+    c.L = c.P = 0.0;
+}
+
+__device__ __forceinline__ void fold_comp(SweepSums& t, const SweepComp& c) {
+    for (int a = 0; a < 3; ++a) {
+        t.S[a] += c.S[a];
+        t.Snz[a] += c.Snz[a];
+        t.Q[a] += c.Q[a];
+    }
+    t.L += c.L;
+    t.P += c.P;
+}
+
 // Fixed-order sums of per-family results: block b sums families [b F, (b+1) F) of the
-// count, F = FAM_PER_SLOT, into out[b].
+// count, F = FAM_PER_SLOT, into out[b].  Each thread's run is compensated, the block
+// tree (8 levels) is not.
 __global__ void __launch_bounds__(256)
 k_reduce_fam(const FamilyRes* __restrict__ in, int64_t count, SweepSums* __restrict__ out) {
     constexpr int NT = 256;
     __shared__ SweepSums sh[NT];
     SweepSums t;
     zero_sums(t);
+    SweepComp c;
+    zero_comp(c);
     const int64_t b0 = (int64_t)blockIdx.x * FAM_PER_SLOT;
     const int64_t b1 = b0 + FAM_PER_SLOT < count ? b0 + FAM_PER_SLOT : count;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) {
         const FamilyRes v = in[i];
-        t.S[0] += v.m[0];
-        t.S[1] += v.m[1];
-        t.S[2] += v.m[2];
-        t.L += v.ent;
-        t.P += v.p;
+        for (int a = 0; a < 3; ++a) comp_add(t.S[a], c.S[a], v.m[a]);
+        comp_add(t.L, c.L, v.ent);
+        comp_add(t.P, c.P, v.p);
         t.gap = fmax(t.gap, v.gap);
         t.nu_cnt += v.nu;
         t.count += 1;
         if (v.x != 0) {
             for (int a = 0; a < 3; ++a) {
-                t.Snz[a] += v.m[a];
-                t.Q[a] = fma(v.m[a], v.m[a], t.Q[a]);
+                comp_add(t.Snz[a], c.Snz[a], v.m[a]);
+                comp_add(t.Q[a], c.Q[a], v.m[a] * v.m[a]);
             }
         }
     }
+    fold_comp(t, c);
     sh[threadIdx.x] = t;
     __syncthreads();
     for (int h = NT / 2; h > 0; h >>= 1) {
@@ -1351,7 +1397,22 @@ k_reduce_sweep(const SweepSums* __restrict__ in, int64_t count, SweepSums* __res
     __shared__ SweepSums sh[NT];
     SweepSums t;
     zero_sums(t);
-    for (int64_t i = threadIdx.x; i < count; i += NT) add_sums(t, in[i]);
+    SweepComp c;
+    zero_comp(c);
+    for (int64_t i = threadIdx.x; i < count; i += NT) {
+        const SweepSums v = in[i];
+        for (int a = 0; a < 3; ++a) {
+            comp_add(t.S[a], c.S[a], v.S[a]);
+            comp_add(t.Snz[a], c.Snz[a], v.Snz[a]);
+            comp_add(t.Q[a], c.Q[a], v.Q[a]);
+        }
+        comp_add(t.L, c.L, v.L);
+        comp_add(t.P, c.P, v.P);
+        t.gap = fmax(t.gap, v.gap);
+        t.nu_cnt += v.nu_cnt;
+        t.count += v.count;
+    }
+    fold_comp(t, c);
     sh[threadIdx.x] = t;
     __syncthreads();
     for (int h = NT / 2; h > 0; h >>= 1) {
