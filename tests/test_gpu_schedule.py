@@ -79,7 +79,7 @@ def test_every_schedule_matches_the_oracle(n, dtype):
 def test_set_schedule_rejects_what_does_not_apply():
     ctx = make_ctx(synth.haar_state(18, 8200), pw.PW_C128)
     for args, status in (((15, 0, 0, 0), 8), ((12, 13, 0, 0), 8), ((11, 0, 0, 0), 1), ((0, 0, 3, 0), 1),
-                         ((0, 0, 0, -1), 1)):
+                         ((0, 0, 256, 0), 1), ((0, 0, 0, -1), 1)):
         with pytest.raises(pw.PWError) as e:
             pw.pw_set_schedule(ctx.h, *args)
         assert e.value.status == status, args
