@@ -704,7 +704,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learned-draws", type=int, default=1024)
-    ap.add_argument("--learned-pilot", type=int, default=2048)
+    ap.add_argument("--learned-pilot", type=int, default=4096,
+                    help="exact-marginal pilot draws of the learned proposal (three quarters train the MADE, "
+                         "one quarter judges it)")
     ap.add_argument("--learned-leg", nargs="*", choices=("psi_m", "tdoped"), default=["tdoped"],
                     help="N=30 learned-vs-plain proposal comparison (default: the T-doped state of the workload; "
                          "psi_m shows the learnable case)")
