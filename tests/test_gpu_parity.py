@@ -398,8 +398,10 @@ def test_mc_graph_replay_matches_eager(n, sampler):
 
 
 def test_eval_states_uneven_sizes_match_single_state_calls():
+    # states of one size and dtype share launches (single-workgroup plans at N = 9 and 12,
+    # multi-pass at 15 and 17), states alone in their class run as before
     import torch
-    sizes = [(9, 0), (12, 1), (15, 0), (16, 1), (17, 0), (18, 1)]
+    sizes = [(9, 0), (12, 1), (15, 0), (16, 1), (17, 0), (18, 1), (9, 0), (12, 1), (15, 0), (17, 0)]
     states, tensors, refs = [], [], []
     for k, (n, dt) in enumerate(sizes):
         psi = as_input(synth.haar_state(n, 1200 + k), dt)
@@ -408,7 +410,7 @@ def test_eval_states_uneven_sizes_match_single_state_calls():
         states.append((t, n, dt))
         refs.append(psi)
     rng = np.random.default_rng(5)
-    idx = rng.integers(0, len(sizes), 60).astype(np.int32)
+    idx = rng.integers(0, len(sizes), 100).astype(np.int32)
     xs = np.array([int(rng.integers(0, 1 << sizes[i][0])) for i in idx], dtype=np.uint64)
     log("eval_states %d states, %d families" % (len(sizes), len(xs)))
     ctx = pw.Context(0)
