@@ -138,7 +138,8 @@ PW_API pw_status pw_workspace_size(int n_qubits, pw_dtype dtype, int x_batch, si
  * its scratch from it.  Pass NULL/0 to return to library-owned scratch.  A lent
  * buffer runs the largest launch it holds.  Library-owned scratch is sized for
  * the default launch: up to 256 MiB of half spectra (at most 256 families), and
- * up to 64 families (within 16 GiB) for states of 16 MiB and more, whose
+ * up to sixteen families (64 once a family's half spectrum is 64 MiB or more; within
+ * 16 GiB) for states of 16 MiB and more, whose
  * first pass runs them in one group sharing the state's tiles; lists are
  * then evaluated in order of the top bit of x and the results put back in list
  * order. */

@@ -137,10 +137,13 @@ int default_batch(int n, pw_dtype dt) {
     // power of two
     size_t p = 1;
     while (p * 2 <= b) p *= 2;
-    // states of 16 MiB and more: launches of up to 64 families, which the first pass runs
-    // in one tile-sharing group (up to 16 GiB of half spectra; measured per family against
-    // launches of 16: complex64 N = 24 -4 %, 26 -3.5 %, 27 -3 %, complex128 N = 24 -2 %)
-    while (p < 64 && first_pass_group(P, dt == PW_C128, 16) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
+    // states of 16 MiB and more: launches of up to sixteen families, which the first pass
+    // runs in one tile-sharing group (up to 16 GiB of half spectra); up to 64 once a family's
+    // half spectrum is 64 MiB or more, where the MALL holds no batch anyway (measured per
+    // family against launches of 16: complex64 N = 24 -4 %, 26 -3.5 %, 27 -3 %, complex128
+    // N = 24 -2 %)
+    const size_t cap = per >= ((size_t)64 << 20) ? 64 : 16;
+    while (p < cap && first_pass_group(P, dt == PW_C128, 16) > 1 && 2 * p * per <= ((size_t)16 << 30)) p *= 2;
     return (int)p;
 }
 
