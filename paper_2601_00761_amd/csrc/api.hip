@@ -1581,6 +1581,7 @@ pw_status pw_mixed(pw_ctx c, int n_a, double eps, pw_mixed_result* out) {
     return PW_OK;
 }
 
+extern "C++" {
 namespace {
 // Candidate schedules of the bound state: the plan variants that apply (first pass of 12 or
 // 15 bits, column tiles of 12 / 13 / 15 bits) crossed with the first-pass groups that the
@@ -1618,6 +1619,7 @@ std::vector<Schedule> schedule_candidates(pw_ctx c) {
     return out;
 }
 }  // namespace
+}  // extern "C++"
 
 pw_status pw_autotune(pw_ctx c, int* best_batch, int* candidates, double* us_per_family, int* n_candidates) {
     pw_status s = check_state(c);
