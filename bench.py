@@ -625,6 +625,30 @@ def sigma_leg(pw, torch, ctx, seed, budget_s, per_family_s, precondition_s):
             "note": "wall_s = preconditioning + pilots + sampling to the target"}
 
 
+def mfma_probe(pw, torch, stream):
+    """A small split-BF16 evaluation for matrix-core counters: an N = 20 Haar state in
+    complex64, 256 random x (x != 0) in four launches of 64 families; each launch's first
+    pass is one k_first_mfma of 2^7 tiles x 64 families."""
+    import numpy as np
+    import synth
+    n = N_QUBITS
+    psi = synth.haar_state(n, synth.SEED_BASE + 20).astype(np.complex64)
+    ctx = pw.Context(0, stream)
+    ctx.upload(psi, pw.PW_C64, x_batch=64)
+    pw.pw_set_precision(ctx.h, pw.PW_PREC_BF16X2)
+    pw.pw_set_moments(ctx.h, 2)
+    xs = np.random.default_rng(synth.SEED_BASE).integers(1, 1 << n, size=256, dtype=np.uint64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.eval_x(xs, 1e-4)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": "N=20 Haar state, complex64, split-BF16 transform, 256 x in launches of 64",
+            "families": len(xs), "seconds": el, "sum_m2": float(np.sum(r["m"][:, 0])),
+            "mfma_flops_per_launch": 64 * 2 ** 19 / 256 * 4 * 16384}
+
+
 def sweep20_leg(pw, torch, stream, steps, warmup, steps_c128, timing_every, max_alpha):
     """Exact enumeration of all 4^20 Pauli strings of the N = 20 T-doped Clifford state
     (eta = 20, N_T = 20): complex64 (FP32 transform) and complex128 (FP64)."""
@@ -698,6 +722,9 @@ def main():
                     help="the sigma leg is shortened so that the whole run stays within this many seconds")
     ap.add_argument("--only-n20", action="store_true",
                     help="run only the N=20 exact-enumeration legs and print them (profiling; not a benchmark line)")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="run only a small split-BF16 evaluation (N=20 Haar state, 256 x in launches of 64) for "
+                         "matrix-core counters (profiling; not a benchmark line)")
     ap.add_argument("--sweep-steps", type=int, default=2, help="timed N=20 exact sweeps in complex64 (0: skip)")
     ap.add_argument("--steps-c128", type=int, default=1)
     ap.add_argument("--timing-every", type=int, default=16, help="N=20 leg: time every k-th launch of each class")
@@ -739,6 +766,9 @@ def main():
     if args.only_n20:
         print(json.dumps(sweep20_leg(pw, torch, stream, max(args.sweep_steps, 1), 1, args.steps_c128,
                                      args.timing_every, args.max_alpha)), flush=True)
+        return
+    if args.mfma_probe:
+        print(json.dumps(mfma_probe(pw, torch, stream)), flush=True)
         return
     ctx, seed, pre_s = headline_state(pw, torch, stream, args.eta)
     note("headline state prepared and preconditioned")
