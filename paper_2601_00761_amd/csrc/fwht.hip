@@ -1279,10 +1279,11 @@ __device__ __forceinline__ void comp_add(double& s, double& c, double v) {
     s = t;
 }
 
-// Per-family fixed-order sum of the final pass's partials.  Grid: one wave per family.
-// Each lane's run over the partials is compensated; the wave tree (6 levels) is not.
-template <int MOM>
-__global__ void __launch_bounds__(64)
+// Per-family fixed-order sum of the final pass's partials.  Grid: one workgroup of NT
+// threads per family (one wave, or four for families of 16384 partials and more).  Each
+// thread's run over the partials is compensated; the tree above it is not.
+template <int MOM, int NT>
+__global__ void __launch_bounds__(NT)
 k_finalize(const FamilyRes* __restrict__ parts, int nblk, int n, FamilyRes* __restrict__ out) {
     const FamilyRes* p = parts + (size_t)blockIdx.x * nblk;
     AccD a;
@@ -1290,7 +1291,7 @@ k_finalize(const FamilyRes* __restrict__ parts, int nblk, int n, FamilyRes* __re
     a.gap = -1.0;
     a.cnt = 0u;
     double c1 = 0.0, ce = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += 64) {
+    for (int i = threadIdx.x; i < nblk; i += NT) {
         const AccD b = acc_of(p[i]);
         comp_add(a.s1, c1, b.s1);
         comp_add(a.ent, ce, b.ent);
@@ -1305,8 +1306,22 @@ k_finalize(const FamilyRes* __restrict__ parts, int nblk, int n, FamilyRes* __re
     a.s2 += c2;
     a.s3 += c3;
     a.s4 += c4;
-    a = wave_reduce<64>(a);
+    if constexpr (NT == 64) {
+        a = wave_reduce<64>(a);
+    } else {
+        __shared__ AccD sh[NT / 64];
+        a = block_reduce<NT, MOM>(a, sh);
+    }
     if (threadIdx.x == 0) out[blockIdx.x] = finish<MOM>(a, p[0].x, n);
+}
+
+// Launch of k_finalize for nfam families of nblk partials each.
+template <int MOM>
+void launch_finalize(const FamilyRes* parts, int nblk, int n, int64_t nfam, FamilyRes* out, hipStream_t st) {
+    if (nblk >= 16384)
+        hipLaunchKernelGGL((k_finalize<MOM, 256>), dim3((unsigned)nfam), dim3(256), 0, st, parts, nblk, n, out);
+    else
+        hipLaunchKernelGGL((k_finalize<MOM, 64>), dim3((unsigned)nfam), dim3(64), 0, st, parts, nblk, n, out);
 }
 
 __device__ __forceinline__ void zero_sums(SweepSums& t) {
@@ -1670,7 +1685,7 @@ first_done:
         if (err != hipSuccess) return err;
     }
     if (!finalize) return hipSuccess;
-    hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
+    launch_finalize<MOM>(parts, P.blocks_last, P.n, nb, out, st);
     return hipGetLastError();
 }
 
@@ -1868,9 +1883,9 @@ hipError_t finalize_families(const Plan& P, int max_alpha, const FamilyRes* part
     if (P.fused || nfam <= 0) return hipSuccess;
     if (nfam > 0x7fffffff) return hipErrorInvalidValue;
     if (max_alpha >= 4)
-        hipLaunchKernelGGL((k_finalize<4>), dim3((unsigned)nfam), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
+        launch_finalize<4>(parts, P.blocks_last, P.n, nfam, out, st);
     else
-        hipLaunchKernelGGL((k_finalize<2>), dim3((unsigned)nfam), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
+        launch_finalize<2>(parts, P.blocks_last, P.n, nfam, out, st);
     return hipGetLastError();
 }
 
@@ -1906,7 +1921,7 @@ hipError_t eval_reduced_mp_t(const Plan& P, const void* D, uint64_t x0, int nb, 
                                                 parts, st, nullptr);
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL((k_finalize<MOM>), dim3(nb), dim3(64), 0, st, parts, P.blocks_last, P.n, out);
+    launch_finalize<MOM>(parts, P.blocks_last, P.n, nb, out, st);
     return hipGetLastError();
 }
 
