@@ -353,8 +353,10 @@ PW_API pw_status pw_autotune_load(const char* path, int* loaded);
 
 /* Several states of different sizes in one call: family xs[i] of state
  * states[state_idx[i]], results to out[i] (host arrays).  One workspace serves all
- * states, sized for the largest layout; each state runs at its own families per
- * launch.  Every state with families is norm-checked before any family is
+ * states, sized for the largest layout.  States of the same n and dtype form a class whose
+ * families run as one list, launches spanning its states (each family reads its own
+ * state's address), at that size's families per launch; results are bitwise those of one
+ * pw_eval_x call per state.  Every state with families is norm-checked before any family is
  * evaluated (PW_ERR_NOT_NORMALIZED names the first bad one; out is then untouched).
  * The call synchronises the stream twice, staging x lists and results through
  * library-owned pinned host memory.  The bound state of the context is kept, also
