@@ -139,6 +139,55 @@ __device__ __forceinline__ uint32_t padi(uint32_t i) { return i + (i >> 4); }
 
 template <int K> struct Lds { static constexpr int elems = (1 << K) + ((1 << K) >> 4); };
 
+// The butterflies of reg_stages (below) over register bits [B0, B1), taken depth first:
+// the 2^M registers from OFF are finished over their own bits below M - 1 before the
+// stage on bit M - 1 joins the two halves.  Each point still takes its bits from low to
+// high and each butterfly sees the operands it sees in the stage-by-stage order, so the
+// results are identical; but the stages of the registers loaded first can run while the
+// later loads are still in flight.  DepthFirst1 takes one array of parts (real or
+// imaginary), DepthFirst both parts of each point together.
+template <typename R, int RL, int B0, int B1, int OFF, int M>
+struct DepthFirst1 {
+    static __device__ __forceinline__ void run(R (&v)[1 << RL]) {
+        if constexpr (M > 0) {
+            DepthFirst1<R, RL, B0, B1, OFF, M - 1>::run(v);
+            DepthFirst1<R, RL, B0, B1, OFF + (1 << (M - 1)), M - 1>::run(v);
+            constexpr int b = M - 1;
+            if constexpr (b >= B0 && b < B1) {
+#pragma unroll
+                for (int i = 0; i < (1 << b); ++i) {
+                    const int j = OFF + i, k = j + (1 << b);
+                    const R a = v[j], c = v[k];
+                    v[j] = a + c;
+                    v[k] = a - c;
+                }
+            }
+        }
+    }
+};
+
+template <typename R, int RL, int B0, int B1, int OFF, int M>
+struct DepthFirst {
+    static __device__ __forceinline__ void run(R (&re)[1 << RL], R (&im)[1 << RL]) {
+        if constexpr (M > 0) {
+            DepthFirst<R, RL, B0, B1, OFF, M - 1>::run(re, im);
+            DepthFirst<R, RL, B0, B1, OFF + (1 << (M - 1)), M - 1>::run(re, im);
+            constexpr int b = M - 1;
+            if constexpr (b >= B0 && b < B1) {
+#pragma unroll
+                for (int i = 0; i < (1 << b); ++i) {
+                    const int j = OFF + i, k = j + (1 << b);
+                    const R ar = re[j], ai = im[j], br = re[k], bi = im[k];
+                    re[j] = ar + br;
+                    im[j] = ai + bi;
+                    re[k] = ar - br;
+                    im[k] = ai - bi;
+                }
+            }
+        }
+    }
+};
+
 // Radix-2 butterflies (u, v) -> (u + v, u - v) over register bits [B0, B1).
 template <typename R, int RL, int B0, int B1>
 __device__ __forceinline__ void reg_stages(R (&re)[1 << RL], R (&im)[1 << RL]) {
@@ -194,7 +243,18 @@ __device__ __forceinline__ void exchange(R (&re)[1 << RL], R (&im)[1 << RL], cx<
 template <int RL>
 __host__ __device__ constexpr uint32_t pads(uint32_t i) { return i + (i >> RL); }
 
-template <typename R, int TL, int RL, int AO, int AN, bool TRAIL = true>
+// An empty statement that reads and writes every element: the arithmetic before it stays
+// before it (the compiler otherwise sinks the butterflies below the next barrier).
+template <typename R, int RL>
+__device__ __forceinline__ void settle(R (&v)[1 << RL]) {
+#pragma unroll
+    for (int j = 0; j < (1 << RL); ++j) asm volatile("" : "+v"(v[j]));
+}
+
+// NB > 0: each part, as soon as it is back in registers, takes its butterflies over
+// register bits [0, NB) depth first (the real parts' while the imaginary parts wait for
+// the buffer): the same operations as the stages after the move, in another order.
+template <typename R, int TL, int RL, int AO, int AN, bool TRAIL = true, int NB = 0>
 __device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL], R* buf) {
     static_assert(RL >= 4, "the split buffer pads one element in 2^min(RL, 5)");
     const uint32_t tid = threadIdx.x;
@@ -205,12 +265,17 @@ __device__ __forceinline__ void exchange_split(R (&re)[1 << RL], R (&im)[1 << RL
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) re[j] = rn[pads<RL>((uint32_t)j << AN)];
+    if constexpr (NB > 0) {
+        DepthFirst1<R, RL, 0, NB, 0, RL>::run(re);
+        settle<R, RL>(re);
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) wo[pads<RL>((uint32_t)j << AO)] = im[j];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < (1 << RL); ++j) im[j] = rn[pads<RL>((uint32_t)j << AN)];
+    if constexpr (NB > 0) DepthFirst1<R, RL, 0, NB, 0, RL>::run(im);
     if constexpr (TRAIL) __syncthreads();
 }
 
@@ -235,27 +300,37 @@ constexpr int final_window() {
 
 // REUSE: the workgroup runs another transform through the same buffer afterwards, so
 // every exchange closes with a barrier; otherwise the last one needs none.
-template <typename R, int TL, int RL, int A, int B0, bool SPLIT, bool REUSE>
+// DF: register stages depth first, on a split move each part's as it arrives.
+template <typename R, int TL, int RL, int A, int B0, bool SPLIT, bool REUSE, bool DF = false>
 struct Rounds {
     static __device__ __forceinline__ void run(R (&re)[1 << RL], R (&im)[1 << RL], void* lds) {
         if constexpr (B0 < TL) {
             constexpr bool trail = REUSE || B0 + RL < TL;
-            if constexpr (SPLIT) exchange_split<R, TL, RL, A, B0, trail>(re, im, (R*)lds);
-            else exchange<R, TL, RL, A, B0, trail>(re, im, (cx<R>*)lds);
             constexpr int B1 = (B0 + RL < TL) ? B0 + RL : TL;
-            reg_stages<R, RL, 0, B1 - B0>(re, im);
-            Rounds<R, TL, RL, B0, B0 + RL, SPLIT, REUSE>::run(re, im, lds);
+            if constexpr (SPLIT && DF) {
+                exchange_split<R, TL, RL, A, B0, trail, B1 - B0>(re, im, (R*)lds);
+            } else {
+                if constexpr (SPLIT) exchange_split<R, TL, RL, A, B0, trail>(re, im, (R*)lds);
+                else exchange<R, TL, RL, A, B0, trail>(re, im, (cx<R>*)lds);
+                if constexpr (DF) DepthFirst<R, RL, 0, B1 - B0, 0, RL>::run(re, im);
+                else reg_stages<R, RL, 0, B1 - B0>(re, im);
+            }
+            Rounds<R, TL, RL, B0, B0 + RL, SPLIT, REUSE, DF>::run(re, im, lds);
         }
     }
 };
 
 // Unnormalised WHT over bits [LO, K) of the tile index.  On entry thread t holds
 // points t + j 2^TL (window TL); on exit the points are in final_window().
-template <typename R, int TL, int RL, int LO, bool SPLIT = false, bool REUSE = false>
+// DF: register stages depth first, starting while the loads are still in flight
+// (the column passes: one workgroup per CU, so only the workgroup itself can fill the
+// wait for its loads and its LDS moves).
+template <typename R, int TL, int RL, int LO, bool SPLIT = false, bool REUSE = false, bool DF = false>
 __device__ __forceinline__ void tile_fwht(R (&re)[1 << RL], R (&im)[1 << RL], void* lds) {
     constexpr int S0 = LO > TL ? LO : TL;
-    reg_stages<R, RL, S0 - TL, RL>(re, im);
-    Rounds<R, TL, RL, TL, LO, SPLIT, REUSE>::run(re, im, lds);
+    if constexpr (DF) DepthFirst<R, RL, S0 - TL, RL, 0, RL>::run(re, im);
+    else reg_stages<R, RL, S0 - TL, RL>(re, im);
+    Rounds<R, TL, RL, TL, LO, SPLIT, REUSE, DF>::run(re, im, lds);
 }
 
 // f values of the half-size problem at half indices (tile << K) + t + j 2^TL
@@ -1210,7 +1285,7 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
     // the FP64 log2 table of the reductions, filled while the loads are in flight
     __shared__ Lg2Entry lg2t[LAST ? Lg2Shared<R>::n : 1];
     if constexpr (LAST && sizeof(R) == 8) lg2_table_init(lg2t);
-    tile_fwht<R, TL, RL, W, SPLIT>(re, im, lds);
+    tile_fwht<R, TL, RL, W, SPLIT, false, true>(re, im, lds);
     if constexpr (!LAST) {
         constexpr int A = final_window<TL, RL, W>();
         const uint32_t T = thread_part<A, RL>(tid);
