@@ -1251,7 +1251,11 @@ k_first_mfma(const cx<float>* __restrict__ psi, const uint64_t* __restrict__ fps
 // (parts[family][block]) instead of writing the spectrum back.
 // SPLIT: the exchange moves real then imaginary parts through one buffer of half the
 // size; STREAM: nontemporal loads and stores (tiles far beyond what the caches hold).
-template <typename R, int TL, int RL, int S, bool LAST, int MOM, bool SPLIT = false, bool STREAM = SPLIT>
+// PF > 0 (single-precision reducing passes of one workgroup per CU): each workgroup takes
+// two tiles, bid and bid + gridDim.x, and issues the loads of the second tile's first PF
+// points (per thread) before it reduces the first, so that those loads overlap the
+// reductions, which nothing else on the CU would.  Each tile's arithmetic is unchanged.
+template <typename R, int TL, int RL, int S, bool LAST, int MOM, bool SPLIT = false, bool STREAM = SPLIT, int PF = 0>
 __global__ void __launch_bounds__(1 << TL)
 k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ xs, uint64_t x0, R eps,
          FamilyRes* __restrict__ parts) {
@@ -1261,6 +1265,59 @@ k_column(cx<R>* __restrict__ work, int n, int lo, const uint64_t* __restrict__ x
     __shared__ __align__(16) char lds[LdsBytes<R, K, SPLIT, RL>::v];
     const int nh = n - 1;
     const int cbits = lo - W;
+    if constexpr (PF > 0) {
+        // block_reduce's barrier (NT > 64) separates the first tile's last LDS reads from the
+        // second tile's first LDS writes
+        static_assert(LAST && sizeof(R) == 4 && NT > 64 && PF <= (1 << RL), "two-tile reducing pass");
+        const uint32_t GX = gridDim.x;
+        const uint32_t bid = (GX & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (GX >> 3) + (blockIdx.x >> 3);
+        const uint32_t slot = blockIdx.y;
+        const uint32_t tid = threadIdx.x;
+        constexpr uint32_t WM = (1u << W) - 1u;
+        auto tile_at = [&](uint32_t t) -> const cx<R>* {
+            const uint32_t cb = t & ((1u << cbits) - 1u), hb = t >> cbits;
+            return work + ((size_t)slot << nh) + ((size_t)hb << (lo + S)) + ((size_t)cb << W) + (tid & WM) +
+                   ((size_t)(tid >> W) << lo);
+        };
+        // point offsets from a row shift the compiler cannot see through, taken anew for each
+        // group of loads (otherwise it keeps 64 scalar offsets live across both tiles)
+        auto at = [&](int j, int sh) -> size_t {
+            const uint32_t J = (uint32_t)j << TL;
+            return (J & WM) + ((size_t)(J >> W) << sh);
+        };
+        auto fresh = [&]() {
+            int v = lo;
+            asm volatile("" : "+s"(v));
+            return v;
+        };
+        const uint64_t x = (xs ? xs[slot] : x0 + slot) & ((1ull << n) - 1ull);
+        __shared__ AccD shw[NT / 64];
+        R re[1 << RL], im[1 << RL], pre[PF], pim[PF];
+        const cx<R>* p0 = tile_at(bid);
+        const cx<R>* p1 = tile_at(bid + GX);
+        const int l0 = fresh();
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) ld_point<STREAM>(p0 + at(j, l0), re[j], im[j]);
+        tile_fwht<R, TL, RL, W, SPLIT, false, true>(re, im, lds);
+        const int l1 = fresh();
+#pragma unroll
+        for (int j = 0; j < PF; ++j) ld_point<STREAM>(p1 + at(j, l1), pre[j], pim[j]);
+        asm volatile("" ::: "memory");   // those loads stay above the reductions
+        AccD tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, nullptr), shw);
+        if (tid == 0) parts[(size_t)slot * (2u * GX) + bid] = raw_res(tot, x);
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            re[j] = pre[j];
+            im[j] = pim[j];
+        }
+        const int l2 = fresh();
+#pragma unroll
+        for (int j = PF; j < (1 << RL); ++j) ld_point<STREAM>(p1 + at(j, l2), re[j], im[j]);
+        tile_fwht<R, TL, RL, W, SPLIT, false, true>(re, im, lds);
+        tot = block_reduce<NT, MOM>(reduce_points<R, RL, MOM>(re, im, x == 0, eps, nullptr), shw);
+        if (tid == 0) parts[(size_t)slot * (2u * GX) + bid + GX] = raw_res(tot, x);
+        return;
+    }
     // Workgroups are dealt round-robin to the 8 XCDs; when a family has a multiple of
     // 8 blocks, renumber them so that each XCD takes a contiguous range of column
     // blocks and neighbouring (partial-cache-line) columns share its L2.
@@ -1554,6 +1611,9 @@ __global__ void k_signed(const cx<R>* __restrict__ G, int n, uint32_t x, double*
 // K = 13 (512 x 16, 70 KB) when that saves a pass; fused kernels K = n - 1.
 constexpr int K_FIRST = 12;
 constexpr int COL_RL = 4;
+// points per thread of the next tile loaded while the two-tile reducing pass reduces the
+// current one (16 of 64: 32 more VGPRs, no spills; 8 and 24 measured slower)
+constexpr int COL15_PF = 16;
 #ifndef COL15_LTL
 #define COL15_LTL 9
 #endif
@@ -1639,8 +1699,14 @@ hipError_t launch_column15(int s, dim3 grid, cx<float>* work, int n, int lo, con
 #define PW_COL15(S)                                                                                                \
     case S:                                                                                                        \
         if constexpr (LAST) {                                                                                      \
-            PW_LAUNCH(tm, kc, (int)grid.y, (k_column<float, COL15_LTL, 15 - COL15_LTL, S, LAST, MOM, true>), grid,    \
-                      dim3(1 << COL15_LTL), st, work, n, lo, xs, x0, eps, parts);                                     \
+            if ((grid.x & 15u) == 0) {                                                                             \
+                PW_LAUNCH(tm, kc, (int)grid.y,                                                                     \
+                          (k_column<float, COL15_LTL, 15 - COL15_LTL, S, LAST, MOM, true, true, COL15_PF>),        \
+                          dim3(grid.x / 2, grid.y), dim3(1 << COL15_LTL), st, work, n, lo, xs, x0, eps, parts);    \
+            } else {                                                                                               \
+                PW_LAUNCH(tm, kc, (int)grid.y, (k_column<float, COL15_LTL, 15 - COL15_LTL, S, LAST, MOM, true>),    \
+                          grid, dim3(1 << COL15_LTL), st, work, n, lo, xs, x0, eps, parts);                        \
+            }                                                                                                      \
         } else {                                                                                                   \
             PW_LAUNCH(tm, kc, (int)grid.y, (k_column<float, 10, 5, S, LAST, MOM, true>), grid, dim3(1024), st, work, \
                       n, lo, xs, x0, eps, parts);                                                                  \
